@@ -1,0 +1,177 @@
+/*
+ * libttsvd -- TT-SVD of large dense tensors on one AMD Instinct MI355X.
+ *
+ * C ABI.  All entry points take plain pointers and sizes, never throw, and
+ * return an int status (TTSVD_OK or a negative TTSVD_E* code).  On error,
+ * ttsvd_last_error() returns a message for the calling thread.  Arguments are
+ * validated before anything is launched.
+ *
+ * Method: the optimized TSQR TT-SVD (Algorithm 2 of Roehrig-Zoellner, Thies,
+ * Basermann, "Performance of the low-rank tensor-train SVD (TT-SVD) for large
+ * dense tensors on modern multi-core CPUs", arXiv 2102.00104).
+ *
+ * Layout (Sec. 3.1.2, "Memory layout"): every matrix is column-major, and a
+ * tensor X in R^{n_1 x ... x n_d} is stored in Fortran order (i_1 fastest),
+ * so the unfolding ((n_1...n_{j-1}) x (n_j r_j)) of the work tensor is a plain
+ * column-major matrix.  Devices pointers are HIP device memory of the current
+ * device; streams are HIP streams (NULL = the legacy default stream).
+ *
+ * Data types: TTSVD_F64 is the paper's precision.  TTSVD_F32 and TTSVD_BF16
+ * store the data in that type, accumulate block-local products in FP32 and
+ * keep the triangular factors and the small SVD in FP64.
+ */
+#ifndef TTSVD_H
+#define TTSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TTSVD_MAX_D 64
+
+/* Element type of tensors and work matrices. */
+typedef enum ttsvd_dtype {
+    TTSVD_F64 = 0,
+    TTSVD_F32 = 1,
+    TTSVD_BF16 = 2
+} ttsvd_dtype;
+
+/* Status codes. */
+enum {
+    TTSVD_OK = 0,
+    TTSVD_EINVAL = -1,       /* invalid argument (sizes, strides, pointers) */
+    TTSVD_ENOMEM = -2,       /* device or host allocation failed */
+    TTSVD_EHIP = -3,         /* HIP runtime error (also asynchronous ones) */
+    TTSVD_ENONFINITE = -4,   /* a triangular factor is not finite (NaN/Inf input) */
+    TTSVD_EUNSUPPORTED = -5  /* unsupported dtype or size */
+};
+
+/*
+ * ttsvd_tsqr_r -- triangular factor of a Q-less tall-skinny QR.
+ *
+ * Defined by the QR decomposition W = QR (Sec. 2.1.1) as computed by the
+ * rank-preserving Q-less TSQR of Sec. 3.2 (Householder reflections with the
+ * eps_FP safeguard of Algorithm 6, a flat reduction per row block and a
+ * reduction tree over the blocks' triangular factors).
+ *
+ *   W      device, rows x cols, column-major, leading dimension ld >= rows,
+ *          element type dtype.  Read only; never written.
+ *   R      device, FP64, cols x cols, column-major, leading dimension
+ *          ldr >= cols.  On return the upper triangle holds R with
+ *          R^T R = W^T W (up to rounding) and the strict lower triangle is 0.
+ *          If rows < cols only the first rows rows of R are significant;
+ *          rows rows..cols-1 are set to 0.  Row signs are unspecified.
+ *   ws     device workspace of ws_bytes bytes (see ttsvd_tsqr_workspace_size),
+ *          or NULL: the library then uses an internal per-device buffer,
+ *          which serialises calls that share a device.
+ *   stream HIP stream; the call is asynchronous with respect to the host.
+ *
+ * Errors: TTSVD_EINVAL for rows < 1, cols < 1, ld < rows, ldr < cols, NULL
+ * W or R, or a too small ws; TTSVD_EUNSUPPORTED for an unknown dtype;
+ * TTSVD_EHIP for launch failures.
+ */
+int ttsvd_tsqr_r(const void *W, int dtype, int64_t rows, int64_t cols,
+                 int64_t ld, double *R, int64_t ldr, void *ws,
+                 size_t ws_bytes, hipStream_t stream);
+
+/* Bytes of device workspace ttsvd_tsqr_r needs for this shape. */
+size_t ttsvd_tsqr_workspace_size(int dtype, int64_t rows, int64_t cols);
+
+/*
+ * ttsvd_gemm_reshape -- fused tall-skinny matrix product and reshape.
+ *
+ * Defined in Sec. 4.1.2 (TSMM): Y <- reshape(W V, (rows/n_next, n_next*k)),
+ * the step  W^(i-1) <- reshape(W^(i) V_{:,1:r}, ...)  of Algorithm 2.
+ *
+ *   W      device, rows x cols, column-major, ld >= rows, element type dtype.
+ *   V      device, FP64, cols x k, column-major, leading dimension ldv >= cols.
+ *   Y      device, element type dtype: the (rows/n_next) x (n_next*k) matrix
+ *          reshape(W V) in column-major order with leading dimension
+ *          ld_y >= rows/n_next.  Element (i, a) of W V is stored at
+ *          Y[(i mod rows') + ld_y * (i div rows' + n_next * a)],
+ *          rows' = rows / n_next.  Y must not overlap W or V.
+ *   n_next must divide rows (n_next = 1 gives a plain product).
+ *   FP64 data is accumulated in FP64; FP32 and BF16 data in FP32.
+ *
+ * Errors: TTSVD_EINVAL for non-positive sizes, rows % n_next != 0, short
+ * leading dimensions or NULL pointers; TTSVD_EUNSUPPORTED for k > 256.
+ */
+int ttsvd_gemm_reshape(const void *W, int dtype, int64_t rows, int64_t cols,
+                       int64_t ld, const double *V, int64_t ldv, int64_t k,
+                       int64_t n_next, void *Y, int64_t ld_y,
+                       hipStream_t stream);
+
+/* Input tensor of ttsvd_decompose. */
+typedef struct ttsvd_tensor {
+    const void *data;    /* device, Fortran order, element type dtype       */
+    int dtype;           /* ttsvd_dtype                                      */
+    int64_t ld_last;     /* stride (in elements) of the last mode, >= n_1...n_{d-1};
+                            0 means dense                                    */
+    hipStream_t stream;  /* stream all work is enqueued on                   */
+} ttsvd_tensor;
+
+/*
+ * Result of ttsvd_decompose.  Buffers are owned by the library and released
+ * by ttsvd_tt_free.  Indices are 0-based: core j (j = 0..d-1) is the paper's
+ * T^(j+1).
+ */
+typedef struct ttsvd_tt {
+    int d;
+    int64_t dims[TTSVD_MAX_D];
+    int64_t ranks[TTSVD_MAX_D + 1];   /* ranks[0] = ranks[d] = 1              */
+    double *cores[TTSVD_MAX_D];       /* device, FP64, (ranks[j], dims[j], ranks[j+1]), Fortran */
+    double *sigma[TTSVD_MAX_D];       /* host: all singular values of the step that produced core j (j >= 1) */
+    int64_t nsigma[TTSVD_MAX_D];      /* their count K = min(rows, cols) (0 for j = 0) */
+    double discarded2[TTSVD_MAX_D];   /* sum of the discarded sigma^2 of that step */
+    double delta;                     /* truncation threshold delta = tol/sqrt(d-1) ||Sigma||_F */
+    double norm_sigma;                /* ||Sigma||_F of the first step (= ||X||_F) */
+    double err_bound;                 /* sqrt(sum_j discarded2[j]) >= ||X - X~||_F */
+    void *priv;                       /* library internal                     */
+} ttsvd_tt;
+
+/*
+ * ttsvd_decompose -- TT decomposition of a dense tensor (Algorithm 2).
+ *
+ *   X      input tensor (read only).
+ *   dims   n_1..n_d (host array of d values, each >= 1).
+ *   d      number of modes, 1 <= d <= TTSVD_MAX_D.
+ *   r_max  maximal TT rank (>= 1, the REQUIRE clause of Algorithms 1 and 2).
+ *   tol    relative tolerance eps >= 0; delta = eps/sqrt(d-1) * ||Sigma||_F
+ *          of the first step; the rank of each step is min(r_max, r_delta),
+ *          r_delta = min{j : sigma_{j+1}^2 + sigma_{j+2}^2 + ... <= delta^2},
+ *          clamped to [1, K].  tol = 0 means no tolerance: r = min(r_max, K).
+ *   out    filled on success (see ttsvd_tt); release with ttsvd_tt_free.
+ *
+ * On return all work on X->stream has completed (the call synchronises it).
+ * Errors: TTSVD_EINVAL (bad sizes, product of dims overflow, NULL pointers),
+ * TTSVD_EUNSUPPORTED (dtype), TTSVD_ENOMEM, TTSVD_EHIP, TTSVD_ENONFINITE.
+ */
+int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d,
+                    int64_t r_max, double tol, ttsvd_tt *out);
+
+/* Release the buffers of a ttsvd_tt filled by ttsvd_decompose (NULL-safe). */
+void ttsvd_tt_free(ttsvd_tt *tt);
+
+/* Device bytes ttsvd_decompose allocates for this problem (work matrices,
+ * triangular factors, SVD scratch and the output cores), excluding X. */
+size_t ttsvd_footprint_bytes(const int64_t *dims, int d, int64_t r_max,
+                             int dtype);
+
+/* Static description of a status code. */
+const char *ttsvd_strerror(int code);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *ttsvd_last_error(void);
+
+/* Library version string. */
+const char *ttsvd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTSVD_H */
