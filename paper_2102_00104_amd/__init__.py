@@ -1,0 +1,208 @@
+"""libttsvd: TT-SVD of large dense tensors on AMD Instinct MI355X (gfx950).
+
+Thin Python binding over the C ABI declared in ``include/ttsvd.h``.  The
+functions ``ttsvd_tsqr_r``, ``ttsvd_gemm_reshape`` and ``ttsvd_decompose``
+only marshal arguments: every step of the decomposition runs in the HIP
+kernels of ``libttsvd.so``.  PyTorch provides device memory and streams.
+
+The library is loaded on first use; if it has not been built
+(``python -m paper_2102_00104_amd.build``) every call raises -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libttsvd.so")
+
+TTSVD_F64, TTSVD_F32, TTSVD_BF16 = 0, 1, 2
+TTSVD_OK = 0
+MAX_D = 64
+ERRORS = {-1: "TTSVD_EINVAL", -2: "TTSVD_ENOMEM", -3: "TTSVD_EHIP",
+          -4: "TTSVD_ENONFINITE", -5: "TTSVD_EUNSUPPORTED"}
+
+#: every symbol include/ttsvd.h declares
+EXPORTED = ["ttsvd_tsqr_r", "ttsvd_tsqr_workspace_size", "ttsvd_gemm_reshape",
+            "ttsvd_decompose", "ttsvd_tt_free", "ttsvd_footprint_bytes",
+            "ttsvd_strerror", "ttsvd_last_error", "ttsvd_version"]
+
+
+class TTSVDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class TTStruct(ctypes.Structure):
+    """ctypes mirror of ``ttsvd_tt``."""
+    _fields_ = [
+        ("d", ctypes.c_int),
+        ("dims", ctypes.c_int64 * MAX_D),
+        ("ranks", ctypes.c_int64 * (MAX_D + 1)),
+        ("cores", ctypes.c_void_p * MAX_D),
+        ("sigma", ctypes.POINTER(ctypes.c_double) * MAX_D),
+        ("nsigma", ctypes.c_int64 * MAX_D),
+        ("discarded2", ctypes.c_double * MAX_D),
+        ("delta", ctypes.c_double),
+        ("norm_sigma", ctypes.c_double),
+        ("err_bound", ctypes.c_double),
+        ("priv", ctypes.c_void_p),
+    ]
+
+
+class TensorStruct(ctypes.Structure):
+    """ctypes mirror of ``ttsvd_tensor``."""
+    _fields_ = [
+        ("data", ctypes.c_void_p),
+        ("dtype", ctypes.c_int),
+        ("ld_last", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+_hip = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libttsvd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libttsvd.so is not built (%s); run `python -m paper_2102_00104_amd.build`"
+                % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        i64, vp, dp = ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        L.ttsvd_tsqr_r.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, vp, ctypes.c_size_t, vp]
+        L.ttsvd_tsqr_r.restype = ctypes.c_int
+        L.ttsvd_tsqr_workspace_size.argtypes = [ctypes.c_int, i64, i64]
+        L.ttsvd_tsqr_workspace_size.restype = ctypes.c_size_t
+        L.ttsvd_gemm_reshape.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64, i64, vp, i64, vp]
+        L.ttsvd_gemm_reshape.restype = ctypes.c_int
+        L.ttsvd_decompose.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64), ctypes.c_int,
+                                      i64, ctypes.c_double, ctypes.POINTER(TTStruct)]
+        L.ttsvd_decompose.restype = ctypes.c_int
+        L.ttsvd_tt_free.argtypes = [ctypes.POINTER(TTStruct)]
+        L.ttsvd_tt_free.restype = None
+        L.ttsvd_footprint_bytes.argtypes = [ctypes.POINTER(i64), ctypes.c_int, i64, ctypes.c_int]
+        L.ttsvd_footprint_bytes.restype = ctypes.c_size_t
+        L.ttsvd_strerror.argtypes = [ctypes.c_int]
+        L.ttsvd_strerror.restype = ctypes.c_char_p
+        L.ttsvd_last_error.argtypes = []
+        L.ttsvd_last_error.restype = ctypes.c_char_p
+        L.ttsvd_version.argtypes = []
+        L.ttsvd_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _hiprt():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_int, ctypes.c_void_p]
+        _hip.hipMemcpyAsync.restype = ctypes.c_int
+    return _hip
+
+
+def _check(rc: int):
+    if rc != TTSVD_OK:
+        raise TTSVDError(rc, lib().ttsvd_last_error().decode())
+
+
+def dtype_code(t) -> int:
+    import torch
+    return {torch.float64: TTSVD_F64, torch.float32: TTSVD_F32,
+            torch.bfloat16: TTSVD_BF16}[t.dtype]
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ----------------------------------------------------------- C-ABI mirror
+
+def ttsvd_tsqr_r(W, dtype: int, rows: int, cols: int, ld: int, R, ldr: int,
+                 ws=None, ws_bytes: int = 0, stream=None) -> None:
+    """``ttsvd_tsqr_r`` on torch device tensors (raw column-major storage)."""
+    _check(lib().ttsvd_tsqr_r(W.data_ptr(), dtype, rows, cols, ld, R.data_ptr(), ldr,
+                              ws.data_ptr() if ws is not None else None, ws_bytes,
+                              _stream(stream)))
+
+
+def ttsvd_tsqr_workspace_size(dtype: int, rows: int, cols: int) -> int:
+    return int(lib().ttsvd_tsqr_workspace_size(dtype, rows, cols))
+
+
+def ttsvd_gemm_reshape(W, dtype: int, rows: int, cols: int, ld: int, V, ldv: int, k: int,
+                       n_next: int, Y, ld_y: int, stream=None) -> None:
+    """``ttsvd_gemm_reshape`` on torch device tensors (raw column-major storage)."""
+    _check(lib().ttsvd_gemm_reshape(W.data_ptr(), dtype, rows, cols, ld, V.data_ptr(), ldv, k,
+                                    n_next, Y.data_ptr(), ld_y, _stream(stream)))
+
+
+def ttsvd_footprint_bytes(dims: Sequence[int], r_max: int, dtype: int) -> int:
+    arr = (ctypes.c_int64 * len(dims))(*[int(n) for n in dims])
+    return int(lib().ttsvd_footprint_bytes(arr, len(dims), r_max, dtype))
+
+
+@dataclass
+class TT:
+    """Result of ``ttsvd_decompose`` with the cores copied into torch tensors."""
+    dims: List[int]
+    ranks: List[int]
+    cores: list                 # torch float64 device tensors (r_{j-1}, n_j, r_j), Fortran data
+    sigma: List[Optional[list]]
+    discarded2: List[float]
+    delta: float
+    norm_sigma: float
+    err_bound: float
+
+
+def ttsvd_decompose(X, dims: Sequence[int], r_max: int, tol: float, ld_last: int = 0,
+                    stream=None) -> TT:
+    """``ttsvd_decompose`` of the Fortran-ordered device tensor X (flat storage)."""
+    import torch
+    dims = [int(n) for n in dims]
+    d = len(dims)
+    st = _stream(stream)
+    xs = TensorStruct(X.data_ptr(), dtype_code(X), ld_last, st)
+    arr = (ctypes.c_int64 * d)(*dims)
+    out = TTStruct()
+    _check(lib().ttsvd_decompose(ctypes.byref(xs), arr, d, r_max, float(tol), ctypes.byref(out)))
+    try:
+        ranks = [int(out.ranks[i]) for i in range(d + 1)]
+        cores = []
+        for j in range(d):
+            shape = (ranks[j], dims[j], ranks[j + 1])
+            n = shape[0] * shape[1] * shape[2]
+            t = torch.empty(n, dtype=torch.float64, device=X.device)
+            rc = _hiprt().hipMemcpyAsync(t.data_ptr(), out.cores[j], n * 8, 3, st)
+            if rc != 0:
+                raise RuntimeError("hipMemcpyAsync failed: %d" % rc)
+            cores.append(t)
+        torch.cuda.synchronize(X.device)
+        sigma = [None] * d
+        for j in range(1, d):
+            sigma[j] = [out.sigma[j][i] for i in range(int(out.nsigma[j]))]
+        return TT(dims, ranks, cores, sigma, [float(out.discarded2[j]) for j in range(d)],
+                  float(out.delta), float(out.norm_sigma), float(out.err_bound))
+    finally:
+        lib().ttsvd_tt_free(ctypes.byref(out))
+
+
+def core_array(t, shape):
+    """A Fortran-ordered numpy copy of a flat device core."""
+    import numpy as np
+    return np.asarray(t.cpu().numpy()).reshape(shape, order="F")

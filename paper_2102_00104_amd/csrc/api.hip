@@ -1,0 +1,388 @@
+// C ABI of libttsvd and the host driver of the TSQR TT-SVD (Algorithm 2 of
+// arXiv 2102.00104).  Validation happens before anything is enqueued; no C++
+// exception crosses the ABI.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace ttsvd {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+int set_error(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+namespace {
+
+bool valid_dtype(int dt) { return dt == TTSVD_F64 || dt == TTSVD_F32 || dt == TTSVD_BF16; }
+
+// Device state of one decomposition: per-step ranks and discarded energy plus
+// the threshold set by the first step.
+struct DecompState {
+    StepState step[TTSVD_MAX_D];
+    double one;  // 1.0, the 1 x 1 "V" used to copy a single-mode tensor
+};
+
+// Owner of the library-allocated outputs of ttsvd_decompose.
+struct TTPriv {
+    double *cores_dev = nullptr;
+    std::vector<double *> sigma_host;
+};
+
+// Shapes of every step for the rank upper bounds (the no-tolerance ranks).
+struct StepShape {
+    int64_t m, rows, K, rb;  // columns, rows, min(rows, m), rank bound
+};
+
+int plan_steps(const int64_t *dims, int d, int64_t r_max, std::vector<StepShape> &steps,
+               std::vector<int64_t> &rb, int64_t &nbar_out) {
+    int64_t nbar = 1;
+    for (int i = 0; i < d; ++i) {
+        if (dims[i] < 1) return set_error(TTSVD_EINVAL, "dims[%d] = %lld < 1", i, (long long)dims[i]);
+        if (nbar > (int64_t(1) << 62) / dims[i])
+            return set_error(TTSVD_EINVAL, "product of dims overflows");
+        nbar *= dims[i];
+    }
+    nbar_out = nbar;
+    rb.assign(d + 1, 1);
+    steps.assign(d, StepShape{0, 0, 0, 0});
+    int64_t nb = nbar;
+    for (int i = d - 1; i >= 1; --i) {
+        StepShape st;
+        st.m = dims[i] * rb[i + 1];
+        st.rows = nb / st.m;
+        st.K = std::min(st.rows, st.m);
+        st.rb = std::min(r_max, st.K);
+        rb[i] = st.rb;
+        steps[i] = st;
+        nb = st.rows * st.rb;
+    }
+    return TTSVD_OK;
+}
+
+struct Footprint {
+    size_t wbuf[2] = {0, 0};   // ping-pong work matrices (elements)
+    size_t rbuf = 0;           // doubles
+    size_t tsqr_ws = 0;        // bytes
+    size_t svd_ws = 0;         // bytes
+    size_t sigma = 0;          // doubles
+    size_t cores = 0;          // doubles
+    std::vector<size_t> core_off, sigma_off;
+};
+
+Footprint footprint(const int64_t *dims, int d, int dtype, const std::vector<StepShape> &steps,
+                    const std::vector<int64_t> &rb) {
+    Footprint f;
+    f.core_off.assign(d, 0);
+    f.sigma_off.assign(d, 0);
+    for (int i = 0; i < d; ++i) {
+        f.core_off[i] = f.cores;
+        f.cores += (size_t)(rb[i] * dims[i] * rb[i + 1]);
+    }
+    int pp = 0;
+    for (int i = d - 1; i >= 1; --i) {
+        const StepShape &s = steps[i];
+        f.rbuf = std::max(f.rbuf, (size_t)(s.m * s.m));
+        f.tsqr_ws = std::max(f.tsqr_ws, tsqr_workspace_bytes(dtype, s.rows, s.m));
+        f.svd_ws = std::max(f.svd_ws, svd_scratch_bytes(s.K, s.m));
+        f.sigma_off[i] = f.sigma;
+        f.sigma += (size_t)s.K;
+        if (i >= 2) {
+            f.wbuf[pp] = std::max(f.wbuf[pp], (size_t)(s.rows * s.rb));
+            pp ^= 1;
+        }
+    }
+    return f;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+}  // namespace ttsvd
+
+using namespace ttsvd;
+
+extern "C" {
+
+const char *ttsvd_version(void) { return "libttsvd 0.1 (gfx950)"; }
+
+const char *ttsvd_last_error(void) { return g_err; }
+
+const char *ttsvd_strerror(int code) {
+    switch (code) {
+        case TTSVD_OK: return "success";
+        case TTSVD_EINVAL: return "invalid argument";
+        case TTSVD_ENOMEM: return "out of memory";
+        case TTSVD_EHIP: return "HIP runtime error";
+        case TTSVD_ENONFINITE: return "non-finite triangular factor";
+        case TTSVD_EUNSUPPORTED: return "unsupported";
+        default: return "unknown error";
+    }
+}
+
+size_t ttsvd_tsqr_workspace_size(int dtype, int64_t rows, int64_t cols) {
+    if (!valid_dtype(dtype) || rows < 1 || cols < 1 || cols > 1024) return 0;
+    return tsqr_workspace_bytes(dtype, rows, cols);
+}
+
+int ttsvd_tsqr_r(const void *W, int dtype, int64_t rows, int64_t cols, int64_t ld, double *R,
+                 int64_t ldr, void *ws, size_t ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (!W || !R) return set_error(TTSVD_EINVAL, "tsqr_r: NULL pointer");
+    if (rows < 1 || cols < 1 || ld < rows || ldr < cols)
+        return set_error(TTSVD_EINVAL, "tsqr_r: bad sizes rows=%lld cols=%lld ld=%lld ldr=%lld",
+                         (long long)rows, (long long)cols, (long long)ld, (long long)ldr);
+    if (!valid_dtype(dtype)) return set_error(TTSVD_EUNSUPPORTED, "tsqr_r: dtype %d", dtype);
+    if (cols > 1024) return set_error(TTSVD_EUNSUPPORTED, "tsqr_r: cols > 1024");
+    const size_t need = tsqr_workspace_bytes(dtype, rows, cols);
+    void *own = nullptr;
+    if (!ws) {
+        if (hipMallocAsync(&own, need, stream) != hipSuccess)
+            return set_error(TTSVD_ENOMEM, "tsqr_r: workspace of %zu bytes", need);
+        ws = own;
+        ws_bytes = need;
+    } else if (ws_bytes < need) {
+        return set_error(TTSVD_EINVAL, "tsqr_r: workspace %zu < %zu bytes", ws_bytes, need);
+    }
+    int rc = tsqr_launch(W, dtype, rows, cols, ld, R, ldr, ws, ws_bytes, stream);
+    if (own) {
+        hipError_t e = hipFreeAsync(own, stream);
+        if (rc == TTSVD_OK && e != hipSuccess)
+            rc = set_error(TTSVD_EHIP, "tsqr_r: hipFreeAsync: %s", hipGetErrorString(e));
+    }
+    return rc;
+}
+
+int ttsvd_gemm_reshape(const void *W, int dtype, int64_t rows, int64_t cols, int64_t ld,
+                       const double *V, int64_t ldv, int64_t k, int64_t n_next, void *Y,
+                       int64_t ld_y, hipStream_t stream) {
+    clear_error();
+    if (!W || !V || !Y) return set_error(TTSVD_EINVAL, "gemm_reshape: NULL pointer");
+    if (rows < 1 || cols < 1 || k < 1 || n_next < 1 || ld < rows || ldv < cols)
+        return set_error(TTSVD_EINVAL, "gemm_reshape: bad sizes");
+    if (rows % n_next != 0) return set_error(TTSVD_EINVAL, "gemm_reshape: rows %% n_next != 0");
+    if (ld_y < rows / n_next) return set_error(TTSVD_EINVAL, "gemm_reshape: ld_y < rows/n_next");
+    if (cols > (int64_t(1) << 30)) return set_error(TTSVD_EUNSUPPORTED, "gemm_reshape: cols too large");
+    if (k > 256) return set_error(TTSVD_EUNSUPPORTED, "gemm_reshape: k > 256");
+    if (!valid_dtype(dtype)) return set_error(TTSVD_EUNSUPPORTED, "gemm_reshape: dtype %d", dtype);
+    return tsmm_launch(W, dtype, rows, cols, ld, V, 1, ldv, k, n_next, Y, dtype, ld_y, stream);
+}
+
+size_t ttsvd_footprint_bytes(const int64_t *dims, int d, int64_t r_max, int dtype) {
+    if (!dims || d < 1 || d > TTSVD_MAX_D || r_max < 1 || !valid_dtype(dtype)) return 0;
+    std::vector<StepShape> steps;
+    std::vector<int64_t> rb;
+    int64_t nbar;
+    if (plan_steps(dims, d, r_max, steps, rb, nbar) != TTSVD_OK) return 0;
+    Footprint f = footprint(dims, d, dtype, steps, rb);
+    const size_t es = dtype_size(dtype);
+    return align256(f.wbuf[0] * es) + align256(f.wbuf[1] * es) + align256(f.rbuf * 8) +
+           align256(f.tsqr_ws) + align256(f.svd_ws) + align256(f.sigma * 8) +
+           align256(sizeof(DecompState)) + align256(f.cores * 8);
+}
+
+void ttsvd_tt_free(ttsvd_tt *tt) {
+    if (!tt) return;
+    TTPriv *p = (TTPriv *)tt->priv;
+    if (p) {
+        if (p->cores_dev) (void)hipFree(p->cores_dev);
+        for (double *s : p->sigma_host) free(s);
+        delete p;
+    }
+    memset(tt, 0, sizeof(*tt));
+}
+
+int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r_max, double tol,
+                    ttsvd_tt *out) {
+    clear_error();
+    if (!X || !X->data || !dims || !out) return set_error(TTSVD_EINVAL, "decompose: NULL pointer");
+    if (d < 1 || d > TTSVD_MAX_D) return set_error(TTSVD_EINVAL, "decompose: d = %d", d);
+    if (r_max < 1) return set_error(TTSVD_EINVAL, "decompose: r_max < 1");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return set_error(TTSVD_EINVAL, "decompose: tol");
+    if (!valid_dtype(X->dtype)) return set_error(TTSVD_EUNSUPPORTED, "decompose: dtype %d", X->dtype);
+    std::vector<StepShape> steps;
+    std::vector<int64_t> rb;
+    int64_t nbar;
+    int rc = plan_steps(dims, d, r_max, steps, rb, nbar);
+    if (rc != TTSVD_OK) return rc;
+    const int64_t lead = nbar / dims[d - 1];
+    const int64_t ld0 = X->ld_last ? X->ld_last : lead;
+    if (ld0 < lead) return set_error(TTSVD_EINVAL, "decompose: ld_last < n_1...n_{d-1}");
+    for (int i = d - 1; i >= 1; --i)
+        if (steps[i].m > 1024)
+            return set_error(TTSVD_EUNSUPPORTED, "decompose: step with %lld > 1024 columns",
+                             (long long)steps[i].m);
+
+    memset(out, 0, sizeof(*out));
+    const hipStream_t s = X->stream;
+    const int dt = X->dtype;
+    const size_t es = dtype_size(dt);
+    Footprint f = footprint(dims, d, dt, steps, rb);
+
+    TTPriv *priv = new TTPriv();
+    out->priv = priv;
+    out->d = d;
+    for (int i = 0; i < d; ++i) out->dims[i] = dims[i];
+
+    if (hipMalloc(&priv->cores_dev, std::max<size_t>(f.cores, 1) * 8) != hipSuccess) {
+        ttsvd_tt_free(out);
+        return set_error(TTSVD_ENOMEM, "decompose: cores (%zu doubles)", f.cores);
+    }
+    for (int i = 0; i < d; ++i) out->cores[i] = priv->cores_dev + f.core_off[i];
+
+    // One stream-ordered workspace allocation for everything temporary.
+    const size_t o_w0 = 0;
+    const size_t o_w1 = o_w0 + align256(f.wbuf[0] * es);
+    const size_t o_r = o_w1 + align256(f.wbuf[1] * es);
+    const size_t o_tq = o_r + align256(f.rbuf * 8);
+    const size_t o_sv = o_tq + align256(f.tsqr_ws);
+    const size_t o_sg = o_sv + align256(f.svd_ws);
+    const size_t o_st = o_sg + align256(f.sigma * 8);
+    const size_t total = o_st + align256(sizeof(DecompState));
+    char *ws = nullptr;
+    if (hipMallocAsync((void **)&ws, total, s) != hipSuccess) {
+        ttsvd_tt_free(out);
+        return set_error(TTSVD_ENOMEM, "decompose: workspace of %zu bytes", total);
+    }
+    void *wbuf[2] = {ws + o_w0, ws + o_w1};
+    double *Rbuf = (double *)(ws + o_r);
+    void *tq = ws + o_tq;
+    void *sv = ws + o_sv;
+    double *sig_dev = (double *)(ws + o_sg);
+    DecompState *state = (DecompState *)(ws + o_st);
+    DecompState hstate;
+    memset(&hstate, 0, sizeof(hstate));
+    hstate.one = 1.0;
+
+#define TTSVD_STEP_TRY(expr)                  \
+    do {                                      \
+        int rc_ = (expr);                     \
+        if (rc_ != TTSVD_OK) {                \
+            (void)hipFreeAsync(ws, s);        \
+            (void)hipStreamSynchronize(s);    \
+            ttsvd_tt_free(out);               \
+            return rc_;                       \
+        }                                     \
+    } while (0)
+#define TTSVD_STEP_HIP(expr)                                                            \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            TTSVD_STEP_TRY(set_error(TTSVD_EHIP, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+
+    TTSVD_STEP_HIP(hipMemcpyAsync(state, &hstate, sizeof(hstate), hipMemcpyHostToDevice, s));
+
+    std::vector<int64_t> ranks(d + 1, 1);
+    if (d == 1) {
+        TTSVD_STEP_TRY(tsmm_launch(X->data, dt, dims[0], 1, dims[0], &state->one, 1, 1, 1, 1,
+                                   out->cores[0], TTSVD_F64, dims[0], s));
+    } else {
+        const void *Wcur = X->data;
+        int64_t ld = ld0;
+        int64_t nb = nbar;
+        int pp = 0;
+        for (int i = d - 1; i >= 1; --i) {
+            const int64_t m = dims[i] * ranks[i + 1];
+            const int64_t rows = nb / m;
+            const int64_t K = std::min(rows, m);
+            // R from the QR decomposition of W^(i)
+            TTSVD_STEP_TRY(tsqr_launch(Wcur, dt, rows, m, ld, Rbuf, m, tq, f.tsqr_ws, s));
+            // small SVD, rank, core T^(i)
+            TTSVD_STEP_TRY(svd_launch(Rbuf, m, K, m, sig_dev + f.sigma_off[i], out->cores[i],
+                                      r_max, tol, d - 1, i == d - 1, &state->step[i],
+                                      &state->step[d - 1], sv, s));
+            int64_t r;
+            if (tol == 0.0) {
+                r = std::min(r_max, K);
+            } else {
+                StepState hs;
+                TTSVD_STEP_HIP(hipMemcpyAsync(&hs, &state->step[i], sizeof(hs), hipMemcpyDeviceToHost, s));
+                TTSVD_STEP_HIP(hipStreamSynchronize(s));
+                if (hs.nonfinite)
+                    TTSVD_STEP_TRY(set_error(TTSVD_ENONFINITE, "decompose: non-finite sigma in step %d", i + 1));
+                r = hs.rank;
+            }
+            ranks[i] = r;
+            // W^(i-1) = reshape(W^(i) V_{:,1:r}); the last product is core T^(1)
+            const int64_t n_next = dims[i - 1];
+            void *Y = (i >= 2) ? wbuf[pp] : (void *)out->cores[0];
+            const int ydt = (i >= 2) ? dt : TTSVD_F64;
+            const int64_t ld_y = rows / n_next;
+            TTSVD_STEP_TRY(tsmm_launch(Wcur, dt, rows, m, ld, out->cores[i], r, 1, r, n_next, Y,
+                                       ydt, ld_y, s));
+            Wcur = Y;
+            ld = ld_y;
+            nb = rows * r;
+            pp ^= 1;
+        }
+    }
+
+    TTSVD_STEP_HIP(hipMemcpyAsync(&hstate, state, sizeof(hstate), hipMemcpyDeviceToHost, s));
+    std::vector<double> sig_host(std::max<size_t>(f.sigma, 1));
+    if (f.sigma)
+        TTSVD_STEP_HIP(hipMemcpyAsync(sig_host.data(), sig_dev, f.sigma * 8, hipMemcpyDeviceToHost, s));
+    TTSVD_STEP_HIP(hipStreamSynchronize(s));
+    TTSVD_STEP_HIP(hipFreeAsync(ws, s));
+
+    double disc_sum = 0.0;
+    for (int i = d - 1; i >= 1; --i) {
+        const StepState &st = hstate.step[i];
+        if (st.nonfinite) {
+            (void)hipStreamSynchronize(s);
+            ttsvd_tt_free(out);
+            return set_error(TTSVD_ENONFINITE, "decompose: non-finite sigma in step %d", i + 1);
+        }
+        ranks[i] = st.rank;
+        out->discarded2[i] = st.discarded2;
+        disc_sum += st.discarded2;
+        const int64_t K = steps[i].K;  // K only depends on ranks to the right
+        double *h = (double *)malloc(sizeof(double) * (size_t)K);
+        if (!h) {
+            ttsvd_tt_free(out);
+            return set_error(TTSVD_ENOMEM, "decompose: host sigma");
+        }
+        priv->sigma_host.push_back(h);
+        out->sigma[i] = h;
+        out->nsigma[i] = 0;
+    }
+    // Recompute K from the actual ranks (tol > 0 can shrink later steps).
+    {
+        int64_t nb = nbar;
+        for (int i = d - 1; i >= 1; --i) {
+            const int64_t m = dims[i] * ranks[i + 1];
+            const int64_t rows = nb / m;
+            const int64_t K = std::min(rows, m);
+            memcpy(out->sigma[i], sig_host.data() + f.sigma_off[i], sizeof(double) * (size_t)K);
+            out->nsigma[i] = K;
+            nb = rows * ranks[i];
+        }
+    }
+    for (int i = 0; i <= d; ++i) out->ranks[i] = ranks[i];
+    out->norm_sigma = std::sqrt(hstate.step[d - 1 >= 1 ? d - 1 : 0].norm2);
+    out->delta = std::sqrt(hstate.step[d - 1 >= 1 ? d - 1 : 0].delta2);
+    out->err_bound = std::sqrt(disc_sum);
+    (void)hipStreamSynchronize(s);
+    return TTSVD_OK;
+#undef TTSVD_STEP_TRY
+#undef TTSVD_STEP_HIP
+}
+
+}  // extern "C"

@@ -1,0 +1,234 @@
+// Small SVD of the triangular factor, truncation and core emission: the
+// "calculate small SVD", "choose rank" and "T^(i) <- reshape(V^T)" steps of
+// Algorithm 2 of arXiv 2102.00104, in FP64, in one workgroup.
+//
+// SVD: one-sided Jacobi (Hestenes) applied to the K rows of R, i.e. to the
+// columns of A = R^T (K vectors of length m).  Plane rotations of pairs of
+// rows make them mutually orthogonal; then R = J diag(sigma) V^T with the
+// rotated rows b_k = sigma_k V_{:,k}, so sigma_k = ||b_k|| and the right
+// singular vectors are the normalised rotated rows -- no separate V has to
+// be accumulated.  Pairs are visited in round-robin (tournament) order so that
+// the K/2 rotations of one round are independent and run in parallel, one
+// group of lanes per pair.
+//
+// Truncation: delta^2 = tol^2/(d-1) ||Sigma||_F^2 in the first step; the rank
+// is min(r_max, r_delta) with r_delta the smallest j such that
+// sigma_{j+1}^2 + ... <= delta^2 (tails summed from the smallest value),
+// clamped to [1, K]; tol = 0 means r = min(r_max, K).  Singular values below
+// kSigmaFloor are counted as zero in these sums: they are the ~1e-154
+// diagonal entries the eps_FP safeguard of the Householder step leaves for
+// exactly zero columns, not data.
+#include <cmath>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace ttsvd {
+
+constexpr double kSigmaFloor = 1e-150;
+constexpr int kMaxSweeps = 40;
+
+__device__ inline void pair_of(int round, int i, int kp, int &p, int &q) {
+    const int n1 = kp - 1;
+    if (i == 0) {
+        p = 0;
+        q = 1 + round % n1;
+    } else {
+        p = 1 + (round + i) % n1;
+        q = 1 + (round - i + n1) % n1;
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void svd_jacobi_kernel(
+    const double *__restrict__ R, int64_t ldr, int K, int m, int lda, int use_lds,
+    double *__restrict__ gA, double *__restrict__ sigma_out, double *__restrict__ core_out,
+    int64_t r_max, double tol, int dm1, int first, StepState *st, StepState *st0) {
+    extern __shared__ double smem[];
+    __shared__ int rot_count;
+    const int tid = threadIdx.x;
+    const int kp = K + (K & 1);
+    double *A = use_lds ? smem : gA;                         // A[v*lda + e]
+    double *sig = use_lds ? smem + (int64_t)kp * lda : smem;  // K values
+    int *order = (int *)(sig + K);                             // K values
+
+    for (int64_t idx = tid; idx < (int64_t)kp * m; idx += NT) {
+        const int v = (int)(idx / m), e = (int)(idx % m);
+        A[(int64_t)v * lda + e] = (v < K) ? R[v + ldr * e] : 0.0;
+    }
+    __syncthreads();
+
+    const int npairs = kp / 2;
+    int tpp = 64;
+    while (tpp > 1 && tpp * npairs > NT) tpp >>= 1;  // lanes per pair
+    const int groups = NT / tpp;
+    const int sub = tid % tpp;
+    const double thr = std::sqrt((double)m) * 0x1p-52;
+
+    int sweep = 0;
+    for (; sweep < kMaxSweeps; ++sweep) {
+        if (tid == 0) rot_count = 0;
+        __syncthreads();
+        int local = 0;
+        for (int round = 0; round < kp - 1; ++round) {
+            for (int pb = 0; pb < npairs; pb += groups) {
+                const int pi = pb + tid / tpp;
+                if (pi < npairs) {
+                    int p, q;
+                    pair_of(round, pi, kp, p, q);
+                    double *ap = A + (int64_t)p * lda, *aq = A + (int64_t)q * lda;
+                    double al = 0.0, be = 0.0, ga = 0.0;
+                    for (int e = sub; e < m; e += tpp) {
+                        const double x = ap[e], y = aq[e];
+                        al = fma(x, x, al);
+                        be = fma(y, y, be);
+                        ga = fma(x, y, ga);
+                    }
+                    for (int d = tpp >> 1; d >= 1; d >>= 1) {
+                        al += __shfl_xor(al, d, kWave);
+                        be += __shfl_xor(be, d, kWave);
+                        ga += __shfl_xor(ga, d, kWave);
+                    }
+                    if (p < K && q < K && al > 0.0 && be > 0.0 &&
+                        fabs(ga) > thr * std::sqrt(al) * std::sqrt(be)) {
+                        const double zeta = (be - al) / (2.0 * ga);
+                        double t;
+                        if (fabs(zeta) > 1e150)
+                            t = 0.5 / zeta;
+                        else
+                            t = copysign(1.0, zeta) / (fabs(zeta) + std::sqrt(fma(zeta, zeta, 1.0)));
+                        const double c = 1.0 / std::sqrt(fma(t, t, 1.0));
+                        const double s = c * t;
+                        for (int e = sub; e < m; e += tpp) {
+                            const double x = ap[e], y = aq[e];
+                            ap[e] = fma(c, x, -s * y);
+                            aq[e] = fma(s, x, c * y);
+                        }
+                        if (sub == 0) ++local;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (local) atomicAdd(&rot_count, local);
+        __syncthreads();
+        const int rc = rot_count;
+        __syncthreads();
+        if (rc == 0) break;
+    }
+
+    // Singular values and their descending order (stable rank sort).
+    for (int v = tid; v < K; v += NT) {
+        const double *av = A + (int64_t)v * lda;
+        double s2 = 0.0;
+        for (int e = 0; e < m; ++e) s2 = fma(av[e], av[e], s2);
+        sig[v] = std::sqrt(s2);
+    }
+    __syncthreads();
+    // NaN keys sort last (as -1), so the ranks always form a permutation.
+    for (int v = tid; v < K; v += NT) {
+        const double sv = isnan(sig[v]) ? -1.0 : sig[v];
+        int pos = 0;
+        for (int u = 0; u < K; ++u) {
+            const double su = isnan(sig[u]) ? -1.0 : sig[u];
+            pos += (su > sv) || (su == sv && u < v);
+        }
+        order[pos] = v;
+    }
+    __syncthreads();
+
+    __shared__ int64_t rank_sh;
+    if (tid == 0) {
+        int nonfinite = 0;
+        double norm2 = 0.0;
+        for (int i = K - 1; i >= 0; --i) {
+            const double s = sig[order[i]];
+            if (!isfinite(s)) nonfinite = 1;
+            const double se = s > kSigmaFloor ? s : 0.0;
+            norm2 = fma(se, se, norm2);
+        }
+        if (first) {
+            st0->norm2 = norm2;
+            st0->delta2 = (tol * tol / (double)dm1) * norm2;
+        }
+        const double delta2 = st0->delta2;
+        int64_t r;
+        if (tol == 0.0) {
+            r = min<int64_t>(r_max, K);
+        } else {
+            int64_t r_delta = K;
+            double acc = 0.0;
+            for (int i = K - 1; i >= 0; --i) {
+                const double s = sig[order[i]];
+                const double se = s > kSigmaFloor ? s : 0.0;
+                acc = fma(se, se, acc);
+                if (acc <= delta2)
+                    r_delta = i;
+                else
+                    break;
+            }
+            r = max<int64_t>(1, min<int64_t>(min<int64_t>(r_max, r_delta), K));
+        }
+        double disc = 0.0;
+        for (int i = K - 1; i >= (int)r; --i) {
+            const double s = sig[order[i]];
+            const double se = s > kSigmaFloor ? s : 0.0;
+            disc = fma(se, se, disc);
+        }
+        st->rank = r;
+        st->discarded2 = disc;
+        st->sweeps = sweep;
+        st->nonfinite = nonfinite;
+        rank_sh = r;
+    }
+    __syncthreads();
+    const int64_t r = rank_sh;
+    for (int i = tid; i < K; i += NT) sigma_out[i] = sig[order[i]];
+    for (int64_t idx = tid; idx < r * m; idx += NT) {
+        const int a = (int)(idx % r), c = (int)(idx / r);
+        const int v = order[a];
+        core_out[idx] = A[(int64_t)v * lda + c] / sig[v];
+    }
+}
+
+namespace {
+constexpr size_t kLdsBudget = 60 * 1024;
+
+int lda_for(int64_t m) { return (int)(m + ((m % 32) == 0 ? 1 : 0)); }
+
+bool fits_lds(int64_t K, int64_t m) {
+    const int64_t kp = K + (K & 1);
+    return (size_t)(kp * lda_for(m)) * 8 + (size_t)K * 12 <= kLdsBudget;
+}
+}  // namespace
+
+size_t svd_scratch_bytes(int64_t K, int64_t m) {
+    if (fits_lds(K, m)) return 0;
+    const int64_t kp = K + (K & 1);
+    return (size_t)(kp * lda_for(m)) * sizeof(double);
+}
+
+int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma_out,
+               double *core_out, int64_t r_max, double tol, int dm1, int first,
+               StepState *state, StepState *state0, void *scratch, hipStream_t s) {
+    if (K < 1 || m < 1 || K > m || m > 4096)
+        return set_error(TTSVD_EINVAL, "svd: bad shape K=%lld m=%lld", (long long)K, (long long)m);
+    const bool lds = fits_lds(K, m);
+    const int lda = lda_for(m);
+    const int64_t kp = K + (K & 1);
+    size_t shmem = (size_t)K * 12 + 16;
+    if (lds) shmem += (size_t)(kp * lda) * 8;
+    if (K <= 64) {
+        hipLaunchKernelGGL(svd_jacobi_kernel<256>, dim3(1), dim3(256), shmem, s, R, ldr, (int)K,
+                           (int)m, lda, (int)lds, (double *)scratch, sigma_out, core_out, r_max,
+                           tol, dm1, first, state, state0);
+    } else {
+        hipLaunchKernelGGL(svd_jacobi_kernel<1024>, dim3(1), dim3(1024), shmem, s, R, ldr, (int)K,
+                           (int)m, lda, (int)lds, (double *)scratch, sigma_out, core_out, r_max,
+                           tol, dm1, first, state, state0);
+    }
+    TTSVD_HIP_TRY(hipGetLastError());
+    return TTSVD_OK;
+}
+
+}  // namespace ttsvd

@@ -1,0 +1,381 @@
+// Rank-preserving Q-less TSQR (Sec. 3.2 of arXiv 2102.00104) for gfx950.
+//
+// The triangular factor R of a tall-skinny W is computed without forming Q:
+// each wave (m <= 64) or workgroup (m > 64) runs a flat reduction over a
+// contiguous slice of rows, applying the Householder step of Algorithm 6 to
+// [R; M] for every row tile M; the slices' triangular factors are stacked into
+// a (slices*m) x m matrix and reduced the same way, level by level, until one
+// slice remains.  The tree's shape depends only on (rows, m), so results are
+// deterministic.  W is never written.
+//
+// Householder step (Algorithm 6): for column j, the reflector acts on the
+// vector u = (R_jj ; M_{:,j}); with eps the smallest normalized number,
+//   t = ||u||^2 + eps,  alpha = -sign(u_1) sqrt(t + eps),
+//   t <- t - alpha u_1,  u_1 <- u_1 - alpha,  v = u / sqrt(t)   (||v||^2 = 2),
+// R_jj <- alpha, and every trailing column x = (R_jk ; M_{:,k}) becomes
+// x - (v^T x) v.  The eps terms keep the step free of branches and divisions
+// by zero for zero columns.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace ttsvd {
+
+// ----------------------------------------------------------------------------
+// Row-owner wave kernel, m <= M <= 64.
+//
+// Lane l holds rows (tile_base + l + 64 i), i < RPT, of the current row tile
+// and row l of the wave's triangular factor, all in registers.  Column dot
+// products are reduced across the wave with wave_allreduce_vec.
+// ----------------------------------------------------------------------------
+constexpr int kRowsWaves = 4;  // waves (= slices) per workgroup
+
+template <int M, int RPT, typename Tin>
+__global__ __launch_bounds__(kRowsWaves *kWave) void tsqr_rows_kernel(
+    const Tin *__restrict__ W, int64_t rows, int m, int64_t ld,
+    int64_t rows_per_slice, int64_t nslices, double *__restrict__ out,
+    int64_t ld_out, int64_t out_row0_stride, int kvalid) {
+    using T = typename Elem<Tin>::acc;
+    constexpr int CH = (M < 16) ? M : 16;  // trailing columns per reduction
+    __shared__ T red[kRowsWaves][kWave];
+
+    const int lane = lane_id();
+    const int wid = threadIdx.x / kWave;
+    const int64_t slice = (int64_t)blockIdx.x * kRowsWaves + wid;
+    if (slice >= nslices) return;  // uniform per wave
+    const int64_t r0 = slice * rows_per_slice;
+    const int64_t r1 = min(rows, r0 + rows_per_slice);
+    T *lds = red[wid];
+    const T eps = EpsFP<T>::value();
+
+    T R[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) R[k] = T(0);
+    T a[RPT][M];
+
+    for (int64_t base = r0; base < r1; base += (int64_t)kWave * RPT) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int64_t row = base + lane + (int64_t)kWave * i;
+            const bool ok = row < r1;
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                a[i][c] = (ok && c < m) ? Elem<Tin>::load(W + row + ld * c) : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            if (j < m) {
+            const bool own = (lane == j);
+            T s = T(0);
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) s = fma(a[i][j], a[i][j], s);
+            const T rjj = own ? R[j] : T(0);
+            s = fma(rjj, rjj, s);
+            s = wave_sum(s);
+            const T u1 = __shfl(R[j], j, kWave);
+            T t = s + eps;
+            T alpha = dev_sqrt(t + eps);
+            alpha = (u1 > T(0)) ? -alpha : alpha;
+            t = fma(-alpha, u1, t);
+            const T beta = T(1) / dev_sqrt(t);
+            T v[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) v[i] = beta * a[i][j];
+            const T vr = own ? beta * (u1 - alpha) : T(0);
+            if (own) R[j] = alpha;
+#pragma unroll
+            for (int kc = j + 1; kc < M; kc += CH) {
+                if (kc < m) {
+                T p[CH];
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    const int k = kc + q;
+                    if (k < M) {
+                        T acc = vr * R[k];
+#pragma unroll
+                        for (int i = 0; i < RPT; ++i) acc = fma(v[i], a[i][k], acc);
+                        p[q] = acc;
+                    } else {
+                        p[q] = T(0);
+                    }
+                }
+                wave_allreduce_vec<CH>(p, lds);
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    const int k = kc + q;
+                    if (k < M) {
+#pragma unroll
+                        for (int i = 0; i < RPT; ++i) a[i][k] = fma(-p[q], v[i], a[i][k]);
+                        R[k] = fma(-p[q], vr, R[k]);
+                    }
+                }
+                }
+            }
+            }
+        }
+    }
+    // Row `lane` of this slice's factor -> stacked output row slice*m + lane.
+    if (lane < m) {
+        const int64_t orow = slice * out_row0_stride + lane;
+        const bool keep = lane < kvalid;
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+            if (c < m) out[orow + ld_out * c] = keep ? (double)R[c] : 0.0;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Column-owner workgroup kernel, 64 < m <= 256 * CPT.
+//
+// Thread t owns the columns t + 256 c (c < CPT) of the current NB-row tile
+// (registers) and of the workgroup's triangular factor (row-major in global
+// scratch, touched only by the owning thread).  For column j the owner builds
+// the reflector and publishes it through LDS; every thread then updates its
+// own trailing columns with in-thread dot products.
+// ----------------------------------------------------------------------------
+constexpr int kColsThreads = 256;
+
+template <int CPT, int NB, typename Tin>
+__global__ __launch_bounds__(kColsThreads) void tsqr_cols_kernel(
+    const Tin *__restrict__ W, int64_t rows, int m, int64_t ld,
+    int64_t rows_per_slice, int64_t nslices, double *__restrict__ rws,
+    double *__restrict__ out, int64_t ld_out, int64_t out_row0_stride,
+    int kvalid) {
+    using T = typename Elem<Tin>::acc;
+    __shared__ T vbuf[2][NB + 1];
+    const int tid = threadIdx.x;
+    const int64_t slice = blockIdx.x;
+    const int64_t r0 = slice * rows_per_slice;
+    const int64_t r1 = min(rows, r0 + rows_per_slice);
+    double *Rw = rws + slice * (int64_t)m * m;  // row-major: Rw[j*m + k]
+    const T eps = EpsFP<T>::value();
+
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int k = tid + kColsThreads * c;
+        if (k < m)
+            for (int j = 0; j < m; ++j) Rw[(int64_t)j * m + k] = 0.0;
+    }
+
+    T a[CPT][NB];
+    for (int64_t base = r0; base < r1; base += NB) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int k = tid + kColsThreads * c;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int64_t row = base + i;
+                a[c][i] = (k < m && row < r1) ? Elem<Tin>::load(W + row + ld * k) : T(0);
+            }
+        }
+        for (int j = 0; j < m; ++j) {
+            T *buf = vbuf[j & 1];
+            const int owner = j % kColsThreads;
+            const int cj = j / kColsThreads;
+            if (tid == owner) {
+                T x[NB];
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    T xi = a[0][i];
+#pragma unroll
+                    for (int c = 1; c < CPT; ++c) xi = (cj == c) ? a[c][i] : xi;
+                    x[i] = xi;
+                }
+                const T u1 = (T)Rw[(int64_t)j * m + j];
+                T s = u1 * u1;
+#pragma unroll
+                for (int i = 0; i < NB; ++i) s = fma(x[i], x[i], s);
+                T t = s + eps;
+                T alpha = dev_sqrt(t + eps);
+                alpha = (u1 > T(0)) ? -alpha : alpha;
+                t = fma(-alpha, u1, t);
+                const T beta = T(1) / dev_sqrt(t);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) buf[i] = beta * x[i];
+                buf[NB] = beta * (u1 - alpha);
+                Rw[(int64_t)j * m + j] = (double)alpha;
+            }
+            __syncthreads();
+            const T vr = buf[NB];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int k = tid + kColsThreads * c;
+                if (k > j && k < m) {
+                    double *rjk = Rw + (int64_t)j * m + k;
+                    const T rv = (T)*rjk;
+                    T g = vr * rv;
+#pragma unroll
+                    for (int i = 0; i < NB; ++i) g = fma(buf[i], a[c][i], g);
+#pragma unroll
+                    for (int i = 0; i < NB; ++i) a[c][i] = fma(-g, buf[i], a[c][i]);
+                    *rjk = (double)fma(-g, vr, rv);
+                }
+            }
+        }
+        // vbuf parity restarts with the next tile: wait for all readers.
+        __syncthreads();
+    }
+    // Stacked output: factor row j -> out row slice*m + j (owner threads write
+    // their own columns, so no further synchronisation is needed).
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int k = tid + kColsThreads * c;
+        if (k < m)
+            for (int j = 0; j < m; ++j) {
+                const double v = (j <= k && j < kvalid) ? Rw[(int64_t)j * m + k] : 0.0;
+                out[slice * out_row0_stride + j + ld_out * k] = v;
+            }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Planner: the levels of the reduction tree for (rows, m).
+// ----------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kMaxWaveSlices = 2048;  // 256 CUs x 8 waves
+constexpr int64_t kMaxColsSlices = 256;   // one workgroup per CU
+
+struct Level {
+    int64_t rows;            // rows of this level's input
+    int64_t nslices;
+    int64_t rows_per_slice;
+};
+
+int rows_rpt(int M) { return M <= 8 ? 8 : M <= 16 ? 4 : 1; }
+int cols_cpt(int64_t m) { return m <= 256 ? 1 : m <= 512 ? 2 : 4; }
+
+std::vector<Level> plan(int64_t rows, int64_t m) {
+    std::vector<Level> lv;
+    int64_t r = rows;
+    for (;;) {
+        int64_t tile, maxs, min_rows;
+        if (m <= 64) {
+            const int M = (int)cpow2((int)m);
+            tile = (int64_t)kWave * rows_rpt(M);
+            maxs = kMaxWaveSlices;
+            min_rows = std::max<int64_t>(4 * tile, 4 * m);
+        } else {
+            tile = 64 / cols_cpt(m);
+            maxs = kMaxColsSlices;
+            min_rows = std::max<int64_t>(16 * tile, 4 * m);
+        }
+        int64_t ns = std::min<int64_t>(maxs, std::max<int64_t>(1, ceil_div(r, min_rows)));
+        int64_t rps = ceil_div(ceil_div(r, ns), tile) * tile;
+        ns = ceil_div(r, rps);
+        lv.push_back({r, ns, rps});
+        if (ns == 1) break;
+        r = ns * m;
+    }
+    return lv;
+}
+
+size_t level_out_doubles(const Level &l, int64_t m) { return (size_t)(l.nslices * m) * (size_t)m; }
+
+template <typename Tin>
+int launch_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level &l,
+                 double *out, int64_t ld_out, int64_t out_stride, int kvalid,
+                 double *rws, hipStream_t s) {
+    if (m <= 64) {
+        const int M = (int)cpow2((int)m);
+        dim3 grid((unsigned)ceil_div(l.nslices, kRowsWaves)), block(kRowsWaves * kWave);
+#define TTSVD_ROWS_CASE(MM)                                                          \
+    case MM:                                                                         \
+        hipLaunchKernelGGL((tsqr_rows_kernel<MM, (MM <= 8 ? 8 : MM <= 16 ? 4 : 1), Tin>), \
+                           grid, block, 0, s, W, rows, (int)m, ld, l.rows_per_slice,  \
+                           l.nslices, out, ld_out, out_stride, kvalid);               \
+        break;
+        switch (M) {
+            TTSVD_ROWS_CASE(1)
+            TTSVD_ROWS_CASE(2)
+            TTSVD_ROWS_CASE(4)
+            TTSVD_ROWS_CASE(8)
+            TTSVD_ROWS_CASE(16)
+            TTSVD_ROWS_CASE(32)
+            TTSVD_ROWS_CASE(64)
+            default:
+                return set_error(TTSVD_EUNSUPPORTED, "tsqr: bad column bucket %d", M);
+        }
+#undef TTSVD_ROWS_CASE
+    } else {
+        dim3 grid((unsigned)l.nslices), block(kColsThreads);
+        switch (cols_cpt(m)) {
+            case 1:
+                hipLaunchKernelGGL((tsqr_cols_kernel<1, 64, Tin>), grid, block, 0, s, W, rows,
+                                   (int)m, ld, l.rows_per_slice, l.nslices, rws, out, ld_out,
+                                   out_stride, kvalid);
+                break;
+            case 2:
+                hipLaunchKernelGGL((tsqr_cols_kernel<2, 32, Tin>), grid, block, 0, s, W, rows,
+                                   (int)m, ld, l.rows_per_slice, l.nslices, rws, out, ld_out,
+                                   out_stride, kvalid);
+                break;
+            default:
+                hipLaunchKernelGGL((tsqr_cols_kernel<4, 16, Tin>), grid, block, 0, s, W, rows,
+                                   (int)m, ld, l.rows_per_slice, l.nslices, rws, out, ld_out,
+                                   out_stride, kvalid);
+                break;
+        }
+    }
+    TTSVD_HIP_TRY(hipGetLastError());
+    return TTSVD_OK;
+}
+
+}  // namespace
+
+size_t tsqr_workspace_bytes(int dtype, int64_t rows, int64_t m) {
+    (void)dtype;
+    std::vector<Level> lv = plan(rows, m);
+    size_t buf = 0, rws = 0;
+    for (size_t i = 0; i + 1 < lv.size(); ++i) buf = std::max(buf, level_out_doubles(lv[i], m));
+    if (m > 64)
+        for (const Level &l : lv) rws = std::max(rws, (size_t)(l.nslices * m) * (size_t)m);
+    return (2 * buf + rws) * sizeof(double) + 256;
+}
+
+int tsqr_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, double *R,
+                int64_t ldr, void *ws, size_t ws_bytes, hipStream_t s) {
+    if (m > 1024) return set_error(TTSVD_EUNSUPPORTED, "tsqr: cols = %lld > 1024", (long long)m);
+    std::vector<Level> lv = plan(rows, m);
+    size_t buf = 0;
+    for (size_t i = 0; i + 1 < lv.size(); ++i) buf = std::max(buf, level_out_doubles(lv[i], m));
+    if (ws_bytes < tsqr_workspace_bytes(dtype, rows, m))
+        return set_error(TTSVD_EINVAL, "tsqr: workspace too small");
+    double *b0 = (double *)ws;
+    double *b1 = b0 + buf;
+    double *rws = b1 + buf;
+    const int kvalid = (int)std::min<int64_t>(rows, m);
+    const double *in = nullptr;
+    for (size_t i = 0; i < lv.size(); ++i) {
+        const Level &l = lv[i];
+        const bool last = (i + 1 == lv.size());
+        double *out = last ? R : ((i & 1) ? b1 : b0);
+        const int64_t ld_out = last ? ldr : l.nslices * m;
+        const int kv = last ? kvalid : (int)m;
+        int rc;
+        if (i == 0) {
+            switch (dtype) {
+                case TTSVD_F64:
+                    rc = launch_level((const double *)W, rows, m, ld, l, out, ld_out, m, kv, rws, s);
+                    break;
+                case TTSVD_F32:
+                    rc = launch_level((const float *)W, rows, m, ld, l, out, ld_out, m, kv, rws, s);
+                    break;
+                case TTSVD_BF16:
+                    rc = launch_level((const bf16 *)W, rows, m, ld, l, out, ld_out, m, kv, rws, s);
+                    break;
+                default:
+                    return set_error(TTSVD_EUNSUPPORTED, "tsqr: dtype %d", dtype);
+            }
+        } else {
+            rc = launch_level(in, l.rows, m, l.rows, l, out, ld_out, m, kv, rws, s);
+        }
+        if (rc != TTSVD_OK) return rc;
+        in = out;
+    }
+    return TTSVD_OK;
+}
+
+}  // namespace ttsvd
