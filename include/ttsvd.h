@@ -66,8 +66,8 @@ enum {
  *          If rows < cols only the first rows rows of R are significant;
  *          rows rows..cols-1 are set to 0.  Row signs are unspecified.
  *   ws     device workspace of ws_bytes bytes (see ttsvd_tsqr_workspace_size),
- *          or NULL: the library then uses an internal per-device buffer,
- *          which serialises calls that share a device.
+ *          or NULL: the library then allocates it stream-ordered on `stream`
+ *          (hipMallocAsync) and frees it the same way after the launches.
  *   stream HIP stream; the call is asynchronous with respect to the host.
  *
  * Errors: TTSVD_EINVAL for rows < 1, cols < 1, ld < rows, ldr < cols, NULL
@@ -169,6 +169,31 @@ const char *ttsvd_last_error(void);
 
 /* Library version string. */
 const char *ttsvd_version(void);
+
+/*
+ * Kernel timing.  Not part of the method: measurement support for the
+ * roofline report of Sec. 4 (achieved bytes and flops per kernel against the
+ * hardware limits).  While enabled, every kernel the library launches is
+ * bracketed by HIP events recorded on its launch stream, together with the
+ * algorithmic bytes and flops of that launch (a TSQR level reads its input
+ * once; the TSMM reads W once and writes Y once; flops 2 n m^2 and 2 n m k).
+ */
+typedef struct ttsvd_kernel_stat {
+    char name[96];        /* kernel instance, e.g. "tsqr_rows<64,1,f64>"     */
+    int64_t launches;
+    double total_ms;      /* sum of event-measured launch durations          */
+    double bytes;         /* sum of algorithmic bytes                        */
+    double flops;         /* sum of algorithmic flops                        */
+} ttsvd_kernel_stat;
+
+/* Turn recording on (on != 0) or off; returns TTSVD_OK. */
+int ttsvd_profile_enable(int on);
+/* Drop all records. */
+void ttsvd_profile_reset(void);
+/* Aggregate the records by kernel name (waits for their events).  Writes up
+ * to max_stats entries to stats and the number of distinct kernels to
+ * *n_stats.  Errors: TTSVD_EINVAL (NULL pointers), TTSVD_EHIP. */
+int ttsvd_profile_read(ttsvd_kernel_stat *stats, int max_stats, int *n_stats);
 
 #ifdef __cplusplus
 }

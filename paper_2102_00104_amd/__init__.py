@@ -28,7 +28,8 @@ ERRORS = {-1: "TTSVD_EINVAL", -2: "TTSVD_ENOMEM", -3: "TTSVD_EHIP",
 #: every symbol include/ttsvd.h declares
 EXPORTED = ["ttsvd_tsqr_r", "ttsvd_tsqr_workspace_size", "ttsvd_gemm_reshape",
             "ttsvd_decompose", "ttsvd_tt_free", "ttsvd_footprint_bytes",
-            "ttsvd_strerror", "ttsvd_last_error", "ttsvd_version"]
+            "ttsvd_strerror", "ttsvd_last_error", "ttsvd_version",
+            "ttsvd_profile_enable", "ttsvd_profile_reset", "ttsvd_profile_read"]
 
 
 class TTSVDError(RuntimeError):
@@ -51,6 +52,17 @@ class TTStruct(ctypes.Structure):
         ("norm_sigma", ctypes.c_double),
         ("err_bound", ctypes.c_double),
         ("priv", ctypes.c_void_p),
+    ]
+
+
+class KernelStat(ctypes.Structure):
+    """ctypes mirror of ``ttsvd_kernel_stat``."""
+    _fields_ = [
+        ("name", ctypes.c_char * 96),
+        ("launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+        ("flops", ctypes.c_double),
     ]
 
 
@@ -97,6 +109,13 @@ def lib() -> ctypes.CDLL:
         L.ttsvd_last_error.restype = ctypes.c_char_p
         L.ttsvd_version.argtypes = []
         L.ttsvd_version.restype = ctypes.c_char_p
+        L.ttsvd_profile_enable.argtypes = [ctypes.c_int]
+        L.ttsvd_profile_enable.restype = ctypes.c_int
+        L.ttsvd_profile_reset.argtypes = []
+        L.ttsvd_profile_reset.restype = None
+        L.ttsvd_profile_read.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int)]
+        L.ttsvd_profile_read.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -150,6 +169,25 @@ def ttsvd_gemm_reshape(W, dtype: int, rows: int, cols: int, ld: int, V, ldv: int
     """``ttsvd_gemm_reshape`` on torch device tensors (raw column-major storage)."""
     _check(lib().ttsvd_gemm_reshape(W.data_ptr(), dtype, rows, cols, ld, V.data_ptr(), ldv, k,
                                     n_next, Y.data_ptr(), ld_y, _stream(stream)))
+
+
+def ttsvd_profile_enable(on: bool) -> None:
+    _check(lib().ttsvd_profile_enable(1 if on else 0))
+
+
+def ttsvd_profile_reset() -> None:
+    lib().ttsvd_profile_reset()
+
+
+def ttsvd_profile_read() -> list:
+    """[{name, launches, total_ms, bytes, flops}] aggregated by kernel."""
+    n = ctypes.c_int(0)
+    _check(lib().ttsvd_profile_read(None, 0, ctypes.byref(n)))
+    arr = (KernelStat * max(1, n.value))()
+    _check(lib().ttsvd_profile_read(arr, n.value, ctypes.byref(n)))
+    return [dict(name=arr[i].name.decode(), launches=int(arr[i].launches),
+                 total_ms=float(arr[i].total_ms), bytes=float(arr[i].bytes),
+                 flops=float(arr[i].flops)) for i in range(n.value)]
 
 
 def ttsvd_footprint_bytes(dims: Sequence[int], r_max: int, dtype: int) -> int:

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -113,6 +114,25 @@ Footprint footprint(const int64_t *dims, int d, int dtype, const std::vector<Ste
 }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Keep freed stream-ordered allocations in the device's default pool instead
+// of returning them to the driver at every synchronisation, so repeated
+// decompositions reuse their multi-GiB workspaces.
+int keep_pool_memory(hipStream_t s) {
+    static std::mutex mu;
+    static bool done[64] = {false};
+    int dev = 0;
+    TTSVD_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev < 0 || dev >= 64 || done[dev]) return TTSVD_OK;
+    hipMemPool_t pool;
+    TTSVD_HIP_TRY(hipDeviceGetDefaultMemPool(&pool, dev));
+    uint64_t thr = UINT64_MAX;
+    TTSVD_HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    done[dev] = true;
+    (void)s;
+    return TTSVD_OK;
+}
 
 }  // namespace
 }  // namespace ttsvd
@@ -232,6 +252,8 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r
 
     memset(out, 0, sizeof(*out));
     const hipStream_t s = X->stream;
+    rc = keep_pool_memory(s);
+    if (rc != TTSVD_OK) return rc;
     const int dt = X->dtype;
     const size_t es = dtype_size(dt);
     Footprint f = footprint(dims, d, dt, steps, rb);

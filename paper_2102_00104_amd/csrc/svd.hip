@@ -22,6 +22,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "profile.h"
 
 namespace ttsvd {
 
@@ -218,6 +219,8 @@ int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma
     const int64_t kp = K + (K & 1);
     size_t shmem = (size_t)K * 12 + 16;
     if (lds) shmem += (size_t)(kp * lda) * 8;
+    prof_begin(s, K <= 64 ? "svd_jacobi_kernel<256>" : "svd_jacobi_kernel<1024>",
+               (double)(m * m) * 8.0 + (double)(K * m) * 8.0, 0.0);
     if (K <= 64) {
         hipLaunchKernelGGL(svd_jacobi_kernel<256>, dim3(1), dim3(256), shmem, s, R, ldr, (int)K,
                            (int)m, lda, (int)lds, (double *)scratch, sigma_out, core_out, r_max,
@@ -227,6 +230,7 @@ int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma
                            (int)m, lda, (int)lds, (double *)scratch, sigma_out, core_out, r_max,
                            tol, dm1, first, state, state0);
     }
+    prof_end(s);
     TTSVD_HIP_TRY(hipGetLastError());
     return TTSVD_OK;
 }

@@ -10,8 +10,11 @@
 // uses several blocks in grid.y (W is then read once per KB columns).
 // The reshape is pure index arithmetic on the store: element (i, a) of W V
 // goes to Y[(i mod rows') + ld_y (i div rows' + n_next a)], rows' = rows/n_next.
+#include <stdio.h>
+
 #include "common.h"
 #include "kernels.h"
+#include "profile.h"
 
 namespace ttsvd {
 
@@ -94,6 +97,11 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(
     }
 }
 
+template <typename T> struct ElemName;
+template <> struct ElemName<double> { static const char *get() { return "double"; } };
+template <> struct ElemName<float> { static const char *get() { return "float"; } };
+template <> struct ElemName<bf16> { static const char *get() { return "ttsvd::bf16"; } };
+
 template <typename Tin, typename Tout>
 static int tsmm_dispatch(const Tin *W, int64_t rows, int64_t m, int64_t ld, const double *V,
                          int64_t svc, int64_t sva, int64_t k, int64_t n_next, Tout *Y,
@@ -104,9 +112,15 @@ static int tsmm_dispatch(const Tin *W, int64_t rows, int64_t m, int64_t ld, cons
 #define TTSVD_TSMM_CASE(KK, RR)                                                            \
     case KK: {                                                                             \
         dim3 grid((unsigned)ceil_div(rows, (int64_t)kTsmmThreads * RR), (unsigned)ky);     \
+        char name[96];                                                                     \
+        snprintf(name, sizeof(name), "tsmm_kernel<%d, %d, %s, %s>", KK, RR,               \
+                 ElemName<Tin>::get(), ElemName<Tout>::get());                            \
+        prof_begin(s, name, (double)rows * m * sizeof(Tin) + (double)rows * k * sizeof(Tout), \
+                   2.0 * (double)rows * m * k);                                            \
         hipLaunchKernelGGL((tsmm_kernel<KK, RR, Tin, Tout>), grid, dim3(kTsmmThreads), 0,  \
                            s, W, rows, (int)m, ld, V, svc, sva, (int)k, rows_next, n_next, \
                            Y, ld_y);                                                       \
+        prof_end(s);                                                                       \
         break;                                                                             \
     }
     switch (KB) {

@@ -15,11 +15,14 @@
 // R_jj <- alpha, and every trailing column x = (R_jk ; M_{:,k}) becomes
 // x - (v^T x) v.  The eps terms keep the step free of branches and divisions
 // by zero for zero columns.
+#include <stdio.h>
+
 #include <algorithm>
 #include <vector>
 
 #include "common.h"
 #include "kernels.h"
+#include "profile.h"
 
 namespace ttsvd {
 
@@ -275,9 +278,37 @@ std::vector<Level> plan(int64_t rows, int64_t m) {
 size_t level_out_doubles(const Level &l, int64_t m) { return (size_t)(l.nslices * m) * (size_t)m; }
 
 template <typename Tin>
+int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level &l,
+                     double *out, int64_t ld_out, int64_t out_stride, int kvalid,
+                     double *rws, hipStream_t s);
+
+template <typename Tin> const char *tname();
+template <> const char *tname<double>() { return "double"; }
+template <> const char *tname<float>() { return "float"; }
+template <> const char *tname<bf16>() { return "ttsvd::bf16"; }
+
+template <typename Tin>
 int launch_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level &l,
                  double *out, int64_t ld_out, int64_t out_stride, int kvalid,
                  double *rws, hipStream_t s) {
+    char name[96];
+    if (m <= 64) {
+        const int M0 = (int)cpow2((int)m);
+        snprintf(name, sizeof(name), "tsqr_rows_kernel<%d, %d, %s>", M0, rows_rpt(M0), tname<Tin>());
+    } else {
+        const int c = cols_cpt(m);
+        snprintf(name, sizeof(name), "tsqr_cols_kernel<%d, %d, %s>", c, 64 / c, tname<Tin>());
+    }
+    prof_begin(s, name, (double)rows * (double)m * sizeof(Tin), 2.0 * (double)rows * (double)m * (double)m);
+    int rc = launch_level_raw(W, rows, m, ld, l, out, ld_out, out_stride, kvalid, rws, s);
+    prof_end(s);
+    return rc;
+}
+
+template <typename Tin>
+int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level &l,
+                     double *out, int64_t ld_out, int64_t out_stride, int kvalid,
+                     double *rws, hipStream_t s) {
     if (m <= 64) {
         const int M = (int)cpow2((int)m);
         dim3 grid((unsigned)ceil_div(l.nslices, kRowsWaves)), block(kRowsWaves * kWave);

@@ -193,7 +193,7 @@ def test_rank_one_outer_product():
     X = vs[0]
     for v in vs[1:]:
         X = np.multiply.outer(X, v)
-    X = X.reshape(-1, order="F") if False else np.asfortranarray(X).reshape(-1, order="F")
+    X = np.asfortranarray(X).reshape(-1, order="F")
     tt = oracle.ttsvd(X, [3, 4, 2, 5], r_max=10, tol=1e-10)
     assert tt.ranks == [1, 1, 1, 1, 1]
     assert oracle.rel_error(X, oracle.tt_full(tt.cores)) < 1e-14
@@ -249,3 +249,24 @@ def test_small_workload_ranks_and_margin():
     assert tt.ranks == synth.capped_ranks(dims, 4)
     assert min(tt.margins[1:]) > 1e-3          # well-posed rank decisions
     assert oracle.rel_error(X, oracle.tt_full(tt.cores)) < 1e-10
+
+
+# ------------------------------------------------------ Table 3 (model) ---
+
+def test_table3_byte_and_flop_model():
+    from paper_2102_00104_amd import model
+    with open(os.path.join(GOLDEN, "table3_model.txt")) as f:
+        rows = [l.split("|") for l in f if l.strip() and not l.startswith("#")]
+    for case, d, n, r_max, gflop, gbyte in rows:
+        dims = [int(n)] * int(d)
+        ranks = model.no_tol_ranks(dims, int(r_max))
+        assert round(model.flops(dims, ranks) / 1e9) == int(gflop)
+        assert round(model.algorithmic_bytes(dims, ranks, 8) / 1e9) == int(gbyte)
+
+
+def test_model_matches_oracle_shapes():
+    from paper_2102_00104_amd import model
+    dims = [2] * 11
+    X = synth.uniform(dims, seed=20)
+    tt = oracle.ttsvd(X, dims, r_max=5, tol=0.0)
+    assert model.no_tol_ranks(dims, 5) == tt.ranks
