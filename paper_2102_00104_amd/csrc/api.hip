@@ -398,6 +398,12 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r
         }
     }
     for (int i = 0; i <= d; ++i) out->ranks[i] = ranks[i];
+    if (getenv("TTSVD_DEBUG")) {
+        for (int i = d - 1; i >= 1; --i)
+            fprintf(stderr, "[ttsvd] step %d: m=%lld rank=%lld sweeps=%lld discarded2=%.3e\n", i + 1,
+                    (long long)(dims[i] * ranks[i + 1]), (long long)ranks[i],
+                    (long long)hstate.step[i].sweeps, hstate.step[i].discarded2);
+    }
     out->norm_sigma = std::sqrt(hstate.step[d - 1 >= 1 ? d - 1 : 0].norm2);
     out->delta = std::sqrt(hstate.step[d - 1 >= 1 ? d - 1 : 0].delta2);
     out->err_bound = std::sqrt(disc_sum);

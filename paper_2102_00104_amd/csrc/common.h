@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <cfloat>
+#include <type_traits>
 
 #include "ttsvd.h"
 
@@ -63,12 +64,6 @@ __device__ inline float dev_sqrt(float x) { return __builtin_sqrtf(x); }
 
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 
-template <typename T>
-__device__ inline T wave_sum(T v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
 
 constexpr int cpow2(int n) {
     int p = 1;
@@ -79,6 +74,110 @@ constexpr int clog2(int n) {
     int q = 0;
     while ((1 << q) < n) ++q;
     return q;
+}
+
+// Compile-time loop: calls f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Halving exchange across lane halves (distance 32) or across 16-lane rows
+// within each half (distance 16) with the gfx950 permlane swaps: lanes whose
+// distance bit is 0 return lo(l) + lo(partner), the others hi(partner) + hi(l).
+template <int D>
+__device__ __forceinline__ uint32_t swap_u32_lo(uint32_t lo, uint32_t hi, uint32_t &hi_out) {
+    if constexpr (D == 32) {
+        auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+        hi_out = r[1];
+        return r[0];
+    } else {
+        auto r = __builtin_amdgcn_permlane16_swap(lo, hi, false, false);
+        hi_out = r[1];
+        return r[0];
+    }
+}
+template <int D>
+__device__ __forceinline__ double swap_add(double lo, double hi) {
+    uint32_t h0, h1;
+    const uint32_t l0 = swap_u32_lo<D>(__double2loint(lo), __double2loint(hi), h0);
+    const uint32_t l1 = swap_u32_lo<D>(__double2hiint(lo), __double2hiint(hi), h1);
+    return __hiloint2double(l1, l0) + __hiloint2double(h1, h0);
+}
+template <int D>
+__device__ __forceinline__ float swap_add(float lo, float hi) {
+    uint32_t h0;
+    const uint32_t l0 = swap_u32_lo<D>(__float_as_uint(lo), __float_as_uint(hi), h0);
+    return __uint_as_float(l0) + __uint_as_float(h0);
+}
+
+// DPP lane exchange inside 16-lane rows (VALU latency, no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+// Value of the partner lane at "distance" D < 16.  Each control is a perfect
+// matching that pairs the lanes with bit D clear with those with bit D set:
+// D = 1, 2: quad_perm xor; D = 4: row_half_mirror (i <-> 7 - i in each 8
+// lanes); D = 8: row_ror:8 (i <-> i ^ 8 in each 16 lanes).
+template <int D, typename T>
+__device__ __forceinline__ T partner(T x) {
+    static_assert(D == 1 || D == 2 || D == 4 || D == 8, "distance");
+    if constexpr (D == 1) return dpp_mov<0xB1>(x);
+    else if constexpr (D == 2) return dpp_mov<0x4E>(x);
+    else if constexpr (D == 4) return dpp_mov<0x141>(x);
+    else return dpp_mov<0x128>(x);
+}
+
+// x + (value of the partner lane at distance D), D in {1, 2, 4, 8, 16, 32}.
+template <int D, typename T>
+__device__ __forceinline__ T butterfly_add(T x) {
+    if constexpr (D >= 16) return swap_add<D>(x, x);
+    else return x + partner<D>(x);
+}
+
+// Value of lane `src` (wave-uniform) in every lane, via v_readlane.
+__device__ __forceinline__ double read_lane(double x, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float read_lane(float x, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+
+// Sum over the 64 lanes of a wave, returned in every lane.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    v = butterfly_add<1>(v);
+    v = butterfly_add<2>(v);
+    v = butterfly_add<4>(v);
+    v = butterfly_add<8>(v);
+    v = butterfly_add<16>(v);
+    v = butterfly_add<32>(v);
+    return v;
+}
+
+// Sum over aligned groups of G lanes (G in {1, 2, 4, 8, 16, 32, 64}).
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+    if constexpr (G >= 2) v = butterfly_add<1>(v);
+    if constexpr (G >= 4) v = butterfly_add<2>(v);
+    if constexpr (G >= 8) v = butterfly_add<4>(v);
+    if constexpr (G >= 16) v = butterfly_add<8>(v);
+    if constexpr (G >= 32) v = butterfly_add<16>(v);
+    if constexpr (G >= 64) v = butterfly_add<32>(v);
+    return v;
 }
 
 // All-reduce of N values per lane over the 64 lanes of a wave.  On return
@@ -102,13 +201,28 @@ __device__ inline void wave_allreduce_vec(T (&p)[N], T *lds) {
         const bool hi = (lane & d) != 0;
 #pragma unroll
         for (int i = 0; i < half; ++i) {
-            T send = hi ? b[i] : b[half + i];
-            T keep = hi ? b[half + i] : b[i];
-            b[i] = keep + __shfl_xor(send, d, kWave);
+            if (t == 0) {
+                b[i] = swap_add<32>(b[i], b[half + i]);
+            } else if (t == 1) {
+                b[i] = swap_add<16>(b[i], b[half + i]);
+            } else {
+                T send = hi ? b[i] : b[half + i];
+                T keep = hi ? b[half + i] : b[i];
+                if (t == 2) send = partner<8>(send);
+                else if (t == 3) send = partner<4>(send);
+                else if (t == 4) send = partner<2>(send);
+                else send = partner<1>(send);
+                b[i] = keep + send;
+            }
         }
     }
-#pragma unroll
-    for (int d = (32 >> Q); d >= 1; d >>= 1) b[0] += __shfl_xor(b[0], d, kWave);
+    // butterfly over the lane bits not used by the halving stages
+    if (Q <= 0) b[0] = butterfly_add<32>(b[0]);
+    if (Q <= 1) b[0] = butterfly_add<16>(b[0]);
+    if (Q <= 2) b[0] = butterfly_add<8>(b[0]);
+    if (Q <= 3) b[0] = butterfly_add<4>(b[0]);
+    if (Q <= 4) b[0] = butterfly_add<2>(b[0]);
+    if (Q <= 5) b[0] = butterfly_add<1>(b[0]);
     const int key = lane >> (6 - Q);
     if ((lane & ((64 >> Q) - 1)) == 0) lds[key] = b[0];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

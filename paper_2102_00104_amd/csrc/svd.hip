@@ -18,6 +18,8 @@
 // kSigmaFloor are counted as zero in these sums: they are the ~1e-154
 // diagonal entries the eps_FP safeguard of the Householder step leaves for
 // exactly zero columns, not data.
+#include <stdio.h>
+
 #include <cmath>
 
 #include "common.h"
@@ -40,84 +42,15 @@ __device__ inline void pair_of(int round, int i, int kp, int &p, int &q) {
     }
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void svd_jacobi_kernel(
-    const double *__restrict__ R, int64_t ldr, int K, int m, int lda, int use_lds,
-    double *__restrict__ gA, double *__restrict__ sigma_out, double *__restrict__ core_out,
-    int64_t r_max, double tol, int dm1, int first, StepState *st, StepState *st0) {
-    extern __shared__ double smem[];
-    __shared__ int rot_count;
+// Singular values, their descending order, the truncation rule and the core
+// T[a + r c] = b_{order[a]}[c] / sigma_{order[a]} from the K rotated rows
+// A[v * lda + e] (v < K, e < m).  sig and order are K-entry shared arrays.
+template <int NT, typename ARef>
+__device__ void svd_epilogue(ARef A, int lda, int K, int m, double *sig, int *order,
+                             double *__restrict__ sigma_out, double *__restrict__ core_out,
+                             int64_t r_max, double tol, int dm1, int first, int sweep,
+                             StepState *st, StepState *st0) {
     const int tid = threadIdx.x;
-    const int kp = K + (K & 1);
-    double *A = use_lds ? smem : gA;                         // A[v*lda + e]
-    double *sig = use_lds ? smem + (int64_t)kp * lda : smem;  // K values
-    int *order = (int *)(sig + K);                             // K values
-
-    for (int64_t idx = tid; idx < (int64_t)kp * m; idx += NT) {
-        const int v = (int)(idx / m), e = (int)(idx % m);
-        A[(int64_t)v * lda + e] = (v < K) ? R[v + ldr * e] : 0.0;
-    }
-    __syncthreads();
-
-    const int npairs = kp / 2;
-    int tpp = 64;
-    while (tpp > 1 && tpp * npairs > NT) tpp >>= 1;  // lanes per pair
-    const int groups = NT / tpp;
-    const int sub = tid % tpp;
-    const double thr = std::sqrt((double)m) * 0x1p-52;
-
-    int sweep = 0;
-    for (; sweep < kMaxSweeps; ++sweep) {
-        if (tid == 0) rot_count = 0;
-        __syncthreads();
-        int local = 0;
-        for (int round = 0; round < kp - 1; ++round) {
-            for (int pb = 0; pb < npairs; pb += groups) {
-                const int pi = pb + tid / tpp;
-                if (pi < npairs) {
-                    int p, q;
-                    pair_of(round, pi, kp, p, q);
-                    double *ap = A + (int64_t)p * lda, *aq = A + (int64_t)q * lda;
-                    double al = 0.0, be = 0.0, ga = 0.0;
-                    for (int e = sub; e < m; e += tpp) {
-                        const double x = ap[e], y = aq[e];
-                        al = fma(x, x, al);
-                        be = fma(y, y, be);
-                        ga = fma(x, y, ga);
-                    }
-                    for (int d = tpp >> 1; d >= 1; d >>= 1) {
-                        al += __shfl_xor(al, d, kWave);
-                        be += __shfl_xor(be, d, kWave);
-                        ga += __shfl_xor(ga, d, kWave);
-                    }
-                    if (p < K && q < K && al > 0.0 && be > 0.0 &&
-                        fabs(ga) > thr * std::sqrt(al) * std::sqrt(be)) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        double t;
-                        if (fabs(zeta) > 1e150)
-                            t = 0.5 / zeta;
-                        else
-                            t = copysign(1.0, zeta) / (fabs(zeta) + std::sqrt(fma(zeta, zeta, 1.0)));
-                        const double c = 1.0 / std::sqrt(fma(t, t, 1.0));
-                        const double s = c * t;
-                        for (int e = sub; e < m; e += tpp) {
-                            const double x = ap[e], y = aq[e];
-                            ap[e] = fma(c, x, -s * y);
-                            aq[e] = fma(s, x, c * y);
-                        }
-                        if (sub == 0) ++local;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        if (local) atomicAdd(&rot_count, local);
-        __syncthreads();
-        const int rc = rot_count;
-        __syncthreads();
-        if (rc == 0) break;
-    }
-
     // Singular values and their descending order (stable rank sort).
     for (int v = tid; v < K; v += NT) {
         const double *av = A + (int64_t)v * lda;
@@ -192,6 +125,192 @@ __global__ __launch_bounds__(NT) void svd_jacobi_kernel(
     }
 }
 
+__device__ __forceinline__ double sum8(double x) { return group_sum<8>(x); }
+
+// Small-matrix path, K <= m <= MB <= 64: the rows live in LDS, eight lanes
+// work on one pair (each on MB/8 consecutive elements), dot products are
+// reduced with DPP inside the 8-lane group, one barrier per round.
+template <int MB>
+__global__ __launch_bounds__(4 * MB) void svd_small_kernel(
+    const double *__restrict__ R, int64_t ldr, int K, int m, double *__restrict__ sigma_out,
+    double *__restrict__ core_out, int64_t r_max, double tol, int dm1, int first,
+    StepState *st, StepState *st0) {
+    constexpr int NT = 4 * MB;
+    constexpr int E = MB / 8;       // elements per lane
+    constexpr int LDA = MB + 2;     // row stride (keeps 16-byte alignment)
+    __shared__ __attribute__((aligned(16))) double A[MB * LDA];
+    __shared__ double sig[MB];
+    __shared__ int order[MB];
+    __shared__ int rot_count;
+    const int tid = threadIdx.x;
+    const int kp = K + (K & 1);
+    const int n1 = kp - 1;
+
+    for (int idx = tid; idx < MB * MB; idx += NT) {
+        const int vv = idx / MB, e = idx % MB;
+        A[vv * LDA + e] = (vv < K && e < m) ? R[vv + ldr * e] : 0.0;
+    }
+    __syncthreads();
+
+    const int pi = tid / 8;         // pair handled by this group
+    const int sub = tid % 8;
+    const bool active = pi < kp / 2;
+    const double thr = 4.0 * (double)m * 0x1p-52;
+    const double thr2 = thr * thr;
+
+    int sweep = 0;
+    for (; sweep < kMaxSweeps; ++sweep) {
+        if (tid == 0) rot_count = 0;
+        __syncthreads();
+        int local = 0;
+        for (int round = 0; round < n1; ++round) {
+            if (active) {
+                int p, q;
+                if (pi == 0) {
+                    p = 0;
+                    q = 1 + round;
+                } else {
+                    int x = round + pi;
+                    x = x >= n1 ? x - n1 : x;
+                    int y = round - pi;
+                    y = y < 0 ? y + n1 : y;
+                    p = 1 + x;
+                    q = 1 + y;
+                }
+                double *ap = A + p * LDA + sub * E;
+                double *aq = A + q * LDA + sub * E;
+                double x[E], y[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    x[e] = ap[e];
+                    y[e] = aq[e];
+                }
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    al = fma(x[e], x[e], al);
+                    be = fma(y[e], y[e], be);
+                    ga = fma(x[e], y[e], ga);
+                }
+                al = sum8(al);
+                be = sum8(be);
+                ga = sum8(ga);
+                if (ga * ga > thr2 * al * be && al > 0.0 && be > 0.0) {
+                    // rotation zeroing the (p, q) entry of [a_p a_q]^T [a_p a_q]:
+                    // t = 2 ga sign(be - al) / (|be - al| + sqrt((be - al)^2 + 4 ga^2)),
+                    // sign(0) = +1: the smaller root of t^2 + 2 zeta t - 1 = 0,
+                    // zeta = (be - al) / (2 ga), written without dividing by ga.
+                    const double dlt = be - al;
+                    const double g2 = ga + ga;
+                    const double t = (dlt < 0.0 ? -g2 : g2) /
+                                     (fabs(dlt) + std::sqrt(fma(dlt, dlt, g2 * g2)));
+                    const double c = 1.0 / std::sqrt(fma(t, t, 1.0));
+                    const double s = c * t;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        ap[e] = fma(c, x[e], -s * y[e]);
+                        aq[e] = fma(s, x[e], c * y[e]);
+                    }
+                    local += (sub == 0);
+                }
+            }
+            __syncthreads();
+        }
+        if (local) atomicAdd(&rot_count, local);
+        __syncthreads();
+        const int rc = rot_count;
+        __syncthreads();
+        if (rc == 0) break;
+    }
+    svd_epilogue<NT>(A, LDA, K, m, sig, order, sigma_out, core_out, r_max, tol, dm1, first, sweep,
+                     st, st0);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void svd_jacobi_kernel(
+    const double *__restrict__ R, int64_t ldr, int K, int m, int lda, int use_lds,
+    double *__restrict__ gA, double *__restrict__ sigma_out, double *__restrict__ core_out,
+    int64_t r_max, double tol, int dm1, int first, StepState *st, StepState *st0) {
+    extern __shared__ double smem[];
+    __shared__ int rot_count;
+    const int tid = threadIdx.x;
+    const int kp = K + (K & 1);
+    double *A = use_lds ? smem : gA;                         // A[v*lda + e]
+    double *sig = use_lds ? smem + (int64_t)kp * lda : smem;  // K values
+    int *order = (int *)(sig + K);                             // K values
+
+    for (int64_t idx = tid; idx < (int64_t)kp * m; idx += NT) {
+        const int v = (int)(idx / m), e = (int)(idx % m);
+        A[(int64_t)v * lda + e] = (v < K) ? R[v + ldr * e] : 0.0;
+    }
+    __syncthreads();
+
+    const int npairs = kp / 2;
+    int tpp = 64;
+    while (tpp > 1 && tpp * npairs > NT) tpp >>= 1;  // lanes per pair
+    const int groups = NT / tpp;
+    const int sub = tid % tpp;
+    // Rotate while |a_p^T a_q| > 4 m eps ||a_p|| ||a_q||: above the rounding
+    // floor of the computed dot products, so the sweeps terminate, and tight
+    // enough that the normalised rows are orthogonal to ~1e-13.
+    const double thr = 4.0 * (double)m * 0x1p-52;
+
+    int sweep = 0;
+    for (; sweep < kMaxSweeps; ++sweep) {
+        if (tid == 0) rot_count = 0;
+        __syncthreads();
+        int local = 0;
+        for (int round = 0; round < kp - 1; ++round) {
+            for (int pb = 0; pb < npairs; pb += groups) {
+                const int pi = pb + tid / tpp;
+                if (pi < npairs) {
+                    int p, q;
+                    pair_of(round, pi, kp, p, q);
+                    double *ap = A + (int64_t)p * lda, *aq = A + (int64_t)q * lda;
+                    double al = 0.0, be = 0.0, ga = 0.0;
+                    for (int e = sub; e < m; e += tpp) {
+                        const double x = ap[e], y = aq[e];
+                        al = fma(x, x, al);
+                        be = fma(y, y, be);
+                        ga = fma(x, y, ga);
+                    }
+                    for (int d = tpp >> 1; d >= 1; d >>= 1) {
+                        al += __shfl_xor(al, d, kWave);
+                        be += __shfl_xor(be, d, kWave);
+                        ga += __shfl_xor(ga, d, kWave);
+                    }
+                    if (p < K && q < K && al > 0.0 && be > 0.0 &&
+                        fabs(ga) > thr * std::sqrt(al) * std::sqrt(be)) {
+                        const double zeta = (be - al) / (2.0 * ga);
+                        double t;
+                        if (fabs(zeta) > 1e150)
+                            t = 0.5 / zeta;
+                        else
+                            t = copysign(1.0, zeta) / (fabs(zeta) + std::sqrt(fma(zeta, zeta, 1.0)));
+                        const double c = 1.0 / std::sqrt(fma(t, t, 1.0));
+                        const double s = c * t;
+                        for (int e = sub; e < m; e += tpp) {
+                            const double x = ap[e], y = aq[e];
+                            ap[e] = fma(c, x, -s * y);
+                            aq[e] = fma(s, x, c * y);
+                        }
+                        if (sub == 0) ++local;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (local) atomicAdd(&rot_count, local);
+        __syncthreads();
+        const int rc = rot_count;
+        __syncthreads();
+        if (rc == 0) break;
+    }
+
+    svd_epilogue<NT>(A, lda, K, m, sig, order, sigma_out, core_out, r_max, tol, dm1, first, sweep,
+                     st, st0);
+}
+
 namespace {
 constexpr size_t kLdsBudget = 60 * 1024;
 
@@ -219,6 +338,25 @@ int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma
     const int64_t kp = K + (K & 1);
     size_t shmem = (size_t)K * 12 + 16;
     if (lds) shmem += (size_t)(kp * lda) * 8;
+    if (m <= 64) {
+        const int MB = m <= 16 ? 16 : m <= 32 ? 32 : 64;
+        char name[64];
+        snprintf(name, sizeof(name), "svd_small_kernel<%d>", MB);
+        prof_begin(s, name, (double)(m * m) * 8.0 + (double)(K * m) * 8.0, 0.0);
+#define TTSVD_SVD_SMALL(MM)                                                                   \
+    hipLaunchKernelGGL(svd_small_kernel<MM>, dim3(1), dim3(4 * MM), 0, s, R, ldr, (int)K, (int)m, \
+                       sigma_out, core_out, r_max, tol, dm1, first, state, state0)
+        if (MB == 16)
+            TTSVD_SVD_SMALL(16);
+        else if (MB == 32)
+            TTSVD_SVD_SMALL(32);
+        else
+            TTSVD_SVD_SMALL(64);
+#undef TTSVD_SVD_SMALL
+        prof_end(s);
+        TTSVD_HIP_TRY(hipGetLastError());
+        return TTSVD_OK;
+    }
     prof_begin(s, K <= 64 ? "svd_jacobi_kernel<256>" : "svd_jacobi_kernel<1024>",
                (double)(m * m) * 8.0 + (double)(K * m) * 8.0, 0.0);
     if (K <= 64) {

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kRowsWaves *kWave) void tsqr_rows_kernel(
             const T rjj = own ? R[j] : T(0);
             s = fma(rjj, rjj, s);
             s = wave_sum(s);
-            const T u1 = __shfl(R[j], j, kWave);
+            const T u1 = read_lane(R[j], j);
             T t = s + eps;
             T alpha = dev_sqrt(t + eps);
             alpha = (u1 > T(0)) ? -alpha : alpha;
@@ -126,6 +126,119 @@ __global__ __launch_bounds__(kRowsWaves *kWave) void tsqr_rows_kernel(
 #pragma unroll
         for (int c = 0; c < M; ++c)
             if (c < m) out[orow + ld_out * c] = keep ? (double)R[c] : 0.0;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Cooperative row-owner kernel, 8 < m <= M <= 64: NW waves share one row tile.
+//
+// Column k of the tile belongs to wave k mod NW (slot k / NW), so every wave
+// has trailing work at every step.  Lane l of each wave holds the rows
+// (tile_base + l + 64 i), i < RPT, of its columns and row l of the factor R
+// restricted to its columns.  For column j the owning wave builds the
+// reflector and publishes v through LDS (double-buffered, one barrier per
+// column); every wave then updates its own trailing columns.
+// ----------------------------------------------------------------------------
+template <int M, int NW, int RPT, typename Tin>
+__global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
+    const Tin *__restrict__ W, int64_t rows, int m, int64_t ld,
+    int64_t rows_per_slice, int64_t nslices, double *__restrict__ out,
+    int64_t ld_out, int64_t out_row0_stride, int kvalid) {
+    using T = typename Elem<Tin>::acc;
+    constexpr int MW = M / NW;
+    static_assert(MW * NW == M, "M must be a multiple of NW");
+    __shared__ T vbuf[2][RPT][kWave];
+    __shared__ T vrbuf[2];
+    __shared__ T red[NW][kWave];
+
+    const int lane = lane_id();
+    const int w = threadIdx.x / kWave;
+    const int64_t slice = blockIdx.x;
+    const int64_t r0 = slice * rows_per_slice;
+    const int64_t r1 = min(rows, r0 + rows_per_slice);
+    T *lds = red[w];
+    const T eps = EpsFP<T>::value();
+
+    T R[MW];
+#pragma unroll
+    for (int k = 0; k < MW; ++k) R[k] = T(0);
+    T a[RPT][MW];
+
+    for (int64_t base = r0; base < r1; base += (int64_t)kWave * RPT) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int64_t row = base + lane + (int64_t)kWave * i;
+            const bool ok = row < r1;
+#pragma unroll
+            for (int kk = 0; kk < MW; ++kk) {
+                const int c = NW * kk + w;
+                a[i][kk] = (ok && c < m) ? Elem<Tin>::load(W + row + ld * c) : T(0);
+            }
+        }
+        static_for<0, MW>([&](auto jjc) {
+            constexpr int jj = decltype(jjc)::value;
+            constexpr int NT = MW - jj;  // slots jj..MW-1 may trail column j
+            for (int o = 0; o < NW; ++o) {
+                const int j = NW * jj + o;
+                if (j >= m) break;
+                const int buf = j & 1;
+                if (w == o) {
+                    const bool own = (lane == j);
+                    T s = T(0);
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) s = fma(a[i][jj], a[i][jj], s);
+                    const T rjj = own ? R[jj] : T(0);
+                    s = fma(rjj, rjj, s);
+                    s = wave_sum(s);
+                    const T u1 = read_lane(R[jj], j);
+                    T t = s + eps;
+                    T alpha = dev_sqrt(t + eps);
+                    alpha = (u1 > T(0)) ? -alpha : alpha;
+                    t = fma(-alpha, u1, t);
+                    const T beta = T(1) / dev_sqrt(t);
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) vbuf[buf][i][lane] = beta * a[i][jj];
+                    if (own) {
+                        vrbuf[buf] = beta * (u1 - alpha);
+                        R[jj] = alpha;
+                    }
+                }
+                __syncthreads();
+                T v[RPT];
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) v[i] = vbuf[buf][i][lane];
+                const T vr = (lane == j) ? vrbuf[buf] : T(0);
+                const bool first = (w > o);  // slot jj trails column j only in later waves
+                T p[NT];
+#pragma unroll
+                for (int q = 0; q < NT; ++q) {
+                    T acc = vr * R[jj + q];
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) acc = fma(v[i], a[i][jj + q], acc);
+                    p[q] = (q == 0 && !first) ? T(0) : acc;
+                }
+                wave_allreduce_vec<NT>(p, lds);
+#pragma unroll
+                for (int q = 0; q < NT; ++q) {
+                    if (q > 0 || first) {
+#pragma unroll
+                        for (int i = 0; i < RPT; ++i) a[i][jj + q] = fma(-p[q], v[i], a[i][jj + q]);
+                        R[jj + q] = fma(-p[q], vr, R[jj + q]);
+                    }
+                }
+            }
+        });
+        // the first column of the next tile reuses buffer 0
+        __syncthreads();
+    }
+    if (lane < m) {
+        const int64_t orow = slice * out_row0_stride + lane;
+        const bool keep = lane < kvalid;
+#pragma unroll
+        for (int kk = 0; kk < MW; ++kk) {
+            const int c = NW * kk + w;
+            if (c < m) out[orow + ld_out * c] = keep ? (double)R[kk] : 0.0;
+        }
     }
 }
 
@@ -238,8 +351,39 @@ __global__ __launch_bounds__(kColsThreads) void tsqr_cols_kernel(
 // ----------------------------------------------------------------------------
 namespace {
 
-constexpr int64_t kMaxWaveSlices = 2048;  // 256 CUs x 8 waves
-constexpr int64_t kMaxColsSlices = 256;   // one workgroup per CU
+constexpr int64_t kMaxWaveSlices = 2048;  // single-wave slices: 256 CUs x 8 waves
+constexpr int64_t kMaxCoopSlices = 512;   // 4-wave slices: 2 per CU
+constexpr int64_t kMaxColsSlices = 256;   // 256-thread slices: 1 per CU
+constexpr int kCoopWaves = 4;
+
+// Kernel family and shape for m columns.
+enum class Kind { Rows, Coop, Cols };
+struct Shape {
+    Kind kind;
+    int M;       // column bucket (Rows, Coop)
+    int rpt;     // rows per lane per tile (Rows, Coop)
+    int cpt;     // columns per thread (Cols)
+    int64_t tile;
+};
+
+Shape shape_for(int64_t m) {
+    Shape sh{Kind::Cols, 0, 0, 0, 0};
+    if (m <= 8) {
+        sh.kind = Kind::Rows;
+        sh.M = (int)cpow2((int)m);
+        sh.rpt = 8;
+        sh.tile = (int64_t)kWave * sh.rpt;
+    } else if (m <= 64) {
+        sh.kind = Kind::Coop;
+        sh.M = (int)cpow2((int)m);
+        sh.rpt = sh.M == 16 ? 16 : sh.M == 32 ? 8 : 4;
+        sh.tile = (int64_t)kWave * sh.rpt;
+    } else {
+        sh.cpt = m <= 256 ? 1 : m <= 512 ? 2 : 4;
+        sh.tile = 64 / sh.cpt;
+    }
+    return sh;
+}
 
 struct Level {
     int64_t rows;            // rows of this level's input
@@ -247,26 +391,24 @@ struct Level {
     int64_t rows_per_slice;
 };
 
-int rows_rpt(int M) { return M <= 8 ? 8 : M <= 16 ? 4 : 1; }
-int cols_cpt(int64_t m) { return m <= 256 ? 1 : m <= 512 ? 2 : 4; }
-
 std::vector<Level> plan(int64_t rows, int64_t m) {
+    const Shape sh = shape_for(m);
     std::vector<Level> lv;
     int64_t r = rows;
     for (;;) {
-        int64_t tile, maxs, min_rows;
-        if (m <= 64) {
-            const int M = (int)cpow2((int)m);
-            tile = (int64_t)kWave * rows_rpt(M);
+        int64_t maxs, min_rows;
+        if (sh.kind == Kind::Rows) {
             maxs = kMaxWaveSlices;
-            min_rows = std::max<int64_t>(4 * tile, 4 * m);
+            min_rows = std::max<int64_t>(4 * sh.tile, 4 * m);
+        } else if (sh.kind == Kind::Coop) {
+            maxs = kMaxCoopSlices;
+            min_rows = std::max<int64_t>(4 * sh.tile, 4 * m);
         } else {
-            tile = 64 / cols_cpt(m);
             maxs = kMaxColsSlices;
-            min_rows = std::max<int64_t>(16 * tile, 4 * m);
+            min_rows = std::max<int64_t>(16 * sh.tile, 4 * m);
         }
         int64_t ns = std::min<int64_t>(maxs, std::max<int64_t>(1, ceil_div(r, min_rows)));
-        int64_t rps = ceil_div(ceil_div(r, ns), tile) * tile;
+        int64_t rps = ceil_div(ceil_div(r, ns), sh.tile) * sh.tile;
         ns = ceil_div(r, rps);
         lv.push_back({r, ns, rps});
         if (ns == 1) break;
@@ -292,13 +434,14 @@ int launch_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level 
                  double *out, int64_t ld_out, int64_t out_stride, int kvalid,
                  double *rws, hipStream_t s) {
     char name[96];
-    if (m <= 64) {
-        const int M0 = (int)cpow2((int)m);
-        snprintf(name, sizeof(name), "tsqr_rows_kernel<%d, %d, %s>", M0, rows_rpt(M0), tname<Tin>());
-    } else {
-        const int c = cols_cpt(m);
-        snprintf(name, sizeof(name), "tsqr_cols_kernel<%d, %d, %s>", c, 64 / c, tname<Tin>());
-    }
+    const Shape sh = shape_for(m);
+    if (sh.kind == Kind::Rows)
+        snprintf(name, sizeof(name), "tsqr_rows_kernel<%d, %d, %s>", sh.M, sh.rpt, tname<Tin>());
+    else if (sh.kind == Kind::Coop)
+        snprintf(name, sizeof(name), "tsqr_coop_kernel<%d, %d, %d, %s>", sh.M, kCoopWaves, sh.rpt,
+                 tname<Tin>());
+    else
+        snprintf(name, sizeof(name), "tsqr_cols_kernel<%d, %d, %s>", sh.cpt, 64 / sh.cpt, tname<Tin>());
     prof_begin(s, name, (double)rows * (double)m * sizeof(Tin), 2.0 * (double)rows * (double)m * (double)m);
     int rc = launch_level_raw(W, rows, m, ld, l, out, ld_out, out_stride, kvalid, rws, s);
     prof_end(s);
@@ -309,30 +452,43 @@ template <typename Tin>
 int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level &l,
                      double *out, int64_t ld_out, int64_t out_stride, int kvalid,
                      double *rws, hipStream_t s) {
-    if (m <= 64) {
-        const int M = (int)cpow2((int)m);
+    const Shape sh = shape_for(m);
+    if (sh.kind == Kind::Rows) {
         dim3 grid((unsigned)ceil_div(l.nslices, kRowsWaves)), block(kRowsWaves * kWave);
-#define TTSVD_ROWS_CASE(MM)                                                          \
-    case MM:                                                                         \
-        hipLaunchKernelGGL((tsqr_rows_kernel<MM, (MM <= 8 ? 8 : MM <= 16 ? 4 : 1), Tin>), \
-                           grid, block, 0, s, W, rows, (int)m, ld, l.rows_per_slice,  \
-                           l.nslices, out, ld_out, out_stride, kvalid);               \
+#define TTSVD_ROWS_CASE(MM)                                                                 \
+    case MM:                                                                                \
+        hipLaunchKernelGGL((tsqr_rows_kernel<MM, 8, Tin>), grid, block, 0, s, W, rows,     \
+                           (int)m, ld, l.rows_per_slice, l.nslices, out, ld_out, out_stride, \
+                           kvalid);                                                         \
         break;
-        switch (M) {
+        switch (sh.M) {
             TTSVD_ROWS_CASE(1)
             TTSVD_ROWS_CASE(2)
             TTSVD_ROWS_CASE(4)
             TTSVD_ROWS_CASE(8)
-            TTSVD_ROWS_CASE(16)
-            TTSVD_ROWS_CASE(32)
-            TTSVD_ROWS_CASE(64)
             default:
-                return set_error(TTSVD_EUNSUPPORTED, "tsqr: bad column bucket %d", M);
+                return set_error(TTSVD_EUNSUPPORTED, "tsqr: bad column bucket %d", sh.M);
         }
 #undef TTSVD_ROWS_CASE
+    } else if (sh.kind == Kind::Coop) {
+        dim3 grid((unsigned)l.nslices), block(kCoopWaves * kWave);
+#define TTSVD_COOP_CASE(MM, RR)                                                                 \
+    case MM:                                                                                    \
+        hipLaunchKernelGGL((tsqr_coop_kernel<MM, kCoopWaves, RR, Tin>), grid, block, 0, s, W,   \
+                           rows, (int)m, ld, l.rows_per_slice, l.nslices, out, ld_out,          \
+                           out_stride, kvalid);                                                 \
+        break;
+        switch (sh.M) {
+            TTSVD_COOP_CASE(16, 16)
+            TTSVD_COOP_CASE(32, 8)
+            TTSVD_COOP_CASE(64, 4)
+            default:
+                return set_error(TTSVD_EUNSUPPORTED, "tsqr: bad column bucket %d", sh.M);
+        }
+#undef TTSVD_COOP_CASE
     } else {
         dim3 grid((unsigned)l.nslices), block(kColsThreads);
-        switch (cols_cpt(m)) {
+        switch (sh.cpt) {
             case 1:
                 hipLaunchKernelGGL((tsqr_cols_kernel<1, 64, Tin>), grid, block, 0, s, W, rows,
                                    (int)m, ld, l.rows_per_slice, l.nslices, rws, out, ld_out,
