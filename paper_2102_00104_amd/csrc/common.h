@@ -57,6 +57,34 @@ template <> struct EpsFP<float> {
     __device__ static constexpr float value() { return FLT_MIN; }
 };
 
+// 1/sqrt(x) and 1/x from the hardware estimates refined by Newton steps
+// (x normal and positive; each step squares the relative error): two steps
+// in FP64, one in FP32.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+    float y = __builtin_amdgcn_rsqf(x);
+    const float e = fmaf(-x * y, y, 1.0f);
+    return fmaf(0.5f * y, e, y);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 __device__ inline double dev_sqrt(double x) { return __builtin_sqrt(x); }
 __device__ inline float dev_sqrt(float x) { return __builtin_sqrtf(x); }
 
@@ -117,13 +145,13 @@ __device__ __forceinline__ float swap_add(float lo, float hi) {
 // DPP lane exchange inside 16-lane rows (VALU latency, no LDS traffic).
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double x) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
 }
 
 // Value of the partner lane at "distance" D < 16.  Each control is a perfect

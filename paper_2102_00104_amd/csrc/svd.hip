@@ -19,6 +19,7 @@
 // diagonal entries the eps_FP safeguard of the Householder step leaves for
 // exactly zero columns, not data.
 #include <stdio.h>
+#include <stdlib.h>
 
 #include <cmath>
 
@@ -125,18 +126,27 @@ __device__ void svd_epilogue(ARef A, int lda, int K, int m, double *sig, int *or
     }
 }
 
-__device__ __forceinline__ double sum8(double x) { return group_sum<8>(x); }
 
-// Small-matrix path, K <= m <= MB <= 64: the rows live in LDS, eight lanes
-// work on one pair (each on MB/8 consecutive elements), dot products are
-// reduced with DPP inside the 8-lane group, one barrier per round.
-template <int MB>
-__global__ __launch_bounds__(4 * MB) void svd_small_kernel(
+// Rows whose squared norm is below this are left alone by the rotations
+// (eps_FP artefacts of exactly zero columns have squared norms ~1e-308).
+constexpr double kTinyNorm2 = 1e-280;
+// Squared relative off-diagonal above which a sweep is not yet the last.
+constexpr double kBigRel2 = 1e-18;
+
+// Small-matrix path, K <= m <= MB <= 64: the rows live in LDS, LPP lanes
+// work on one pair (LPP lanes), dot products are reduced with DPP inside the
+// group, one barrier per round.  Lane `sub` of a group handles the 16-byte
+// chunks at elements 2 LPP c + 2 sub, so each LDS instruction of a group
+// touches contiguous bytes (no bank conflicts inside the group).
+template <int MB, int LPP>
+__global__ __launch_bounds__(MB / 2 * LPP) void svd_small_kernel(
     const double *__restrict__ R, int64_t ldr, int K, int m, double *__restrict__ sigma_out,
     double *__restrict__ core_out, int64_t r_max, double tol, int dm1, int first,
     StepState *st, StepState *st0) {
-    constexpr int NT = 4 * MB;
-    constexpr int E = MB / 8;       // elements per lane
+    constexpr int NT = MB / 2 * LPP;
+    constexpr int E = MB / LPP;     // elements per lane (E / 2 chunks of two)
+    constexpr int CS = 2 * LPP;     // elements per chunk row of a group
+    static_assert(E % 2 == 0, "two elements per chunk");
     constexpr int LDA = MB + 2;     // row stride (keeps 16-byte alignment)
     __shared__ __attribute__((aligned(16))) double A[MB * LDA];
     __shared__ double sig[MB];
@@ -152,8 +162,8 @@ __global__ __launch_bounds__(4 * MB) void svd_small_kernel(
     }
     __syncthreads();
 
-    const int pi = tid / 8;         // pair handled by this group
-    const int sub = tid % 8;
+    const int pi = tid / LPP;       // pair handled by this group
+    const int sub = tid % LPP;
     const bool active = pi < kp / 2;
     const double thr = 4.0 * (double)m * 0x1p-52;
     const double thr2 = thr * thr;
@@ -163,6 +173,7 @@ __global__ __launch_bounds__(4 * MB) void svd_small_kernel(
         if (tid == 0) rot_count = 0;
         __syncthreads();
         int local = 0;
+        bool big = false;
         for (int round = 0; round < n1; ++round) {
             if (active) {
                 int p, q;
@@ -177,13 +188,13 @@ __global__ __launch_bounds__(4 * MB) void svd_small_kernel(
                     p = 1 + x;
                     q = 1 + y;
                 }
-                double *ap = A + p * LDA + sub * E;
-                double *aq = A + q * LDA + sub * E;
+                double *ap = A + p * LDA + 2 * sub;
+                double *aq = A + q * LDA + 2 * sub;
                 double x[E], y[E];
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    x[e] = ap[e];
-                    y[e] = aq[e];
+                    x[e] = ap[CS * (e / 2) + (e & 1)];
+                    y[e] = aq[CS * (e / 2) + (e & 1)];
                 }
                 double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -192,35 +203,48 @@ __global__ __launch_bounds__(4 * MB) void svd_small_kernel(
                     be = fma(y[e], y[e], be);
                     ga = fma(x[e], y[e], ga);
                 }
-                al = sum8(al);
-                be = sum8(be);
-                ga = sum8(ga);
-                if (ga * ga > thr2 * al * be && al > 0.0 && be > 0.0) {
+                al = group_sum<LPP>(al);
+                be = group_sum<LPP>(be);
+                ga = group_sum<LPP>(ga);
+                const double g2a = ga * ga;
+                if (g2a > thr2 * al * be && al > kTinyNorm2 && be > kTinyNorm2) {
                     // rotation zeroing the (p, q) entry of [a_p a_q]^T [a_p a_q]:
                     // t = 2 ga sign(be - al) / (|be - al| + sqrt((be - al)^2 + 4 ga^2)),
                     // sign(0) = +1: the smaller root of t^2 + 2 zeta t - 1 = 0,
                     // zeta = (be - al) / (2 ga), written without dividing by ga.
                     const double dlt = be - al;
                     const double g2 = ga + ga;
-                    const double t = (dlt < 0.0 ? -g2 : g2) /
-                                     (fabs(dlt) + std::sqrt(fma(dlt, dlt, g2 * g2)));
-                    const double c = 1.0 / std::sqrt(fma(t, t, 1.0));
+                    const double h = fma(dlt, dlt, g2 * g2);
+                    const double den = fabs(dlt) + h * rsqrt_nr(h);
+                    const double t = (dlt < 0.0 ? -g2 : g2) * rcp_nr(den);
+                    const double c = rsqrt_nr(fma(t, t, 1.0));
                     const double s = c * t;
+                    big |= g2a > kBigRel2 * al * be;
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
-                        ap[e] = fma(c, x[e], -s * y[e]);
-                        aq[e] = fma(s, x[e], c * y[e]);
+                        ap[CS * (e / 2) + (e & 1)] = fma(c, x[e], -s * y[e]);
+                        aq[CS * (e / 2) + (e & 1)] = fma(s, x[e], c * y[e]);
                     }
                     local += (sub == 0);
                 }
             }
             __syncthreads();
         }
-        if (local) atomicAdd(&rot_count, local);
+        // rot_count: groups that rotated this sweep (low 16 bits) and groups
+        // that rotated a pair with relative off-diagonal above 1e-9 (high
+        // bits).  Jacobi converges quadratically, so a sweep whose rotations
+        // were all below 1e-9 leaves off-diagonals at the 1e-18 level and
+        // needs no checking sweep.
+        const int contrib = (local ? 1 : 0) + (big ? (1 << 16) : 0);
+        if (contrib && sub == 0) atomicAdd(&rot_count, contrib);
         __syncthreads();
         const int rc = rot_count;
         __syncthreads();
         if (rc == 0) break;
+        if ((rc >> 16) == 0) {
+            ++sweep;
+            break;
+        }
     }
     svd_epilogue<NT>(A, LDA, K, m, sig, order, sigma_out, core_out, r_max, tol, dm1, first, sweep,
                      st, st0);
@@ -328,6 +352,16 @@ size_t svd_scratch_bytes(int64_t K, int64_t m) {
     return (size_t)(kp * lda_for(m)) * sizeof(double);
 }
 
+// Lanes per Jacobi pair of the small-matrix kernel (TTSVD_SVD_LPP = 8 or 16,
+// a tuning override; default 8).
+int svd_lpp() {
+    static int v = [] {
+        const char *e = getenv("TTSVD_SVD_LPP");
+        return (e && atoi(e) == 16) ? 16 : 8;
+    }();
+    return v;
+}
+
 int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma_out,
                double *core_out, int64_t r_max, double tol, int dm1, int first,
                StepState *state, StepState *state0, void *scratch, hipStream_t s) {
@@ -340,18 +374,23 @@ int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma
     if (lds) shmem += (size_t)(kp * lda) * 8;
     if (m <= 64) {
         const int MB = m <= 16 ? 16 : m <= 32 ? 32 : 64;
+        const int lpp = MB == 16 ? 8 : svd_lpp();
         char name[64];
-        snprintf(name, sizeof(name), "svd_small_kernel<%d>", MB);
+        snprintf(name, sizeof(name), "svd_small_kernel<%d, %d>", MB, lpp);
         prof_begin(s, name, (double)(m * m) * 8.0 + (double)(K * m) * 8.0, 0.0);
-#define TTSVD_SVD_SMALL(MM)                                                                   \
-    hipLaunchKernelGGL(svd_small_kernel<MM>, dim3(1), dim3(4 * MM), 0, s, R, ldr, (int)K, (int)m, \
-                       sigma_out, core_out, r_max, tol, dm1, first, state, state0)
+#define TTSVD_SVD_SMALL(MM, LL)                                                                \
+    hipLaunchKernelGGL((svd_small_kernel<MM, LL>), dim3(1), dim3(MM / 2 * LL), 0, s, R, ldr,   \
+                       (int)K, (int)m, sigma_out, core_out, r_max, tol, dm1, first, state, state0)
         if (MB == 16)
-            TTSVD_SVD_SMALL(16);
+            TTSVD_SVD_SMALL(16, 8);
+        else if (MB == 32 && lpp == 16)
+            TTSVD_SVD_SMALL(32, 16);
         else if (MB == 32)
-            TTSVD_SVD_SMALL(32);
+            TTSVD_SVD_SMALL(32, 8);
+        else if (lpp == 16)
+            TTSVD_SVD_SMALL(64, 16);
         else
-            TTSVD_SVD_SMALL(64);
+            TTSVD_SVD_SMALL(64, 8);
 #undef TTSVD_SVD_SMALL
         prof_end(s);
         TTSVD_HIP_TRY(hipGetLastError());

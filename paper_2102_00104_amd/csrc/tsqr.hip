@@ -16,6 +16,7 @@
 // x - (v^T x) v.  The eps terms keep the step free of branches and divisions
 // by zero for zero columns.
 #include <stdio.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <vector>
@@ -135,9 +136,11 @@ __global__ __launch_bounds__(kRowsWaves *kWave) void tsqr_rows_kernel(
 // Column k of the tile belongs to wave k mod NW (slot k / NW), so every wave
 // has trailing work at every step.  Lane l of each wave holds the rows
 // (tile_base + l + 64 i), i < RPT, of its columns and row l of the factor R
-// restricted to its columns.  For column j the owning wave builds the
-// reflector and publishes v through LDS (double-buffered, one barrier per
-// column); every wave then updates its own trailing columns.
+// restricted to its columns.  Reflectors are published through LDS
+// (double-buffered, one barrier per column) with a look-ahead of one: while
+// the other waves apply reflector j to their trailing columns, the wave that
+// owns column j+1 first updates that column, builds reflector j+1 and
+// publishes it, and only then updates the rest of its columns.
 // ----------------------------------------------------------------------------
 template <int M, int NW, int RPT, typename Tin>
 __global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
@@ -164,6 +167,34 @@ __global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
     for (int k = 0; k < MW; ++k) R[k] = T(0);
     T a[RPT][MW];
 
+    // Householder reflector of column jn, held by this wave in slot S
+    // (Algorithm 6): u = (R_jn,jn ; tile column), alpha = -sign(u_1) ||u||,
+    // v = (u - alpha e_1) / sqrt(t) with ||v||^2 = 2, published to LDS.
+    auto reflector = [&](auto slot_c, int jn) {
+        constexpr int S = decltype(slot_c)::value;
+        const bool own = (lane == jn);
+        T s = T(0);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) s = fma(a[i][S], a[i][S], s);
+        const T rjj = own ? R[S] : T(0);
+        s = fma(rjj, rjj, s);
+        s = wave_sum(s);
+        const T u1 = read_lane(R[S], jn);
+        T t = s + eps;
+        const T t2 = t + eps;
+        T alpha = t2 * rsqrt_nr(t2);
+        alpha = (u1 > T(0)) ? -alpha : alpha;
+        t = fma(-alpha, u1, t);
+        const T beta = rsqrt_nr(t);
+        const int buf = jn & 1;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) vbuf[buf][i][lane] = beta * a[i][S];
+        if (own) {
+            vrbuf[buf] = beta * (u1 - alpha);
+            R[S] = alpha;
+        }
+    };
+
     for (int64_t base = r0; base < r1; base += (int64_t)kWave * RPT) {
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
@@ -175,6 +206,7 @@ __global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
                 a[i][kk] = (ok && c < m) ? Elem<Tin>::load(W + row + ld * c) : T(0);
             }
         }
+        if (w == 0) reflector(std::integral_constant<int, 0>{}, 0);
         static_for<0, MW>([&](auto jjc) {
             constexpr int jj = decltype(jjc)::value;
             constexpr int NT = MW - jj;  // slots jj..MW-1 may trail column j
@@ -182,28 +214,7 @@ __global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
                 const int j = NW * jj + o;
                 if (j >= m) break;
                 const int buf = j & 1;
-                if (w == o) {
-                    const bool own = (lane == j);
-                    T s = T(0);
-#pragma unroll
-                    for (int i = 0; i < RPT; ++i) s = fma(a[i][jj], a[i][jj], s);
-                    const T rjj = own ? R[jj] : T(0);
-                    s = fma(rjj, rjj, s);
-                    s = wave_sum(s);
-                    const T u1 = read_lane(R[jj], j);
-                    T t = s + eps;
-                    T alpha = dev_sqrt(t + eps);
-                    alpha = (u1 > T(0)) ? -alpha : alpha;
-                    t = fma(-alpha, u1, t);
-                    const T beta = T(1) / dev_sqrt(t);
-#pragma unroll
-                    for (int i = 0; i < RPT; ++i) vbuf[buf][i][lane] = beta * a[i][jj];
-                    if (own) {
-                        vrbuf[buf] = beta * (u1 - alpha);
-                        R[jj] = alpha;
-                    }
-                }
-                __syncthreads();
+                __syncthreads();  // reflector j is in vbuf[buf]
                 T v[RPT];
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) v[i] = vbuf[buf][i][lane];
@@ -218,17 +229,39 @@ __global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
                     p[q] = (q == 0 && !first) ? T(0) : acc;
                 }
                 wave_allreduce_vec<NT>(p, lds);
+                auto update = [&](int q) {
 #pragma unroll
-                for (int q = 0; q < NT; ++q) {
-                    if (q > 0 || first) {
+                    for (int qq = 0; qq < NT; ++qq) {
+                        if (qq == q) {
 #pragma unroll
-                        for (int i = 0; i < RPT; ++i) a[i][jj + q] = fma(-p[q], v[i], a[i][jj + q]);
-                        R[jj + q] = fma(-p[q], vr, R[jj + q]);
+                            for (int i = 0; i < RPT; ++i) a[i][jj + qq] = fma(-p[qq], v[i], a[i][jj + qq]);
+                            R[jj + qq] = fma(-p[qq], vr, R[jj + qq]);
+                        }
+                    }
+                };
+                // look-ahead: column j+1 is slot jj of wave o+1, or slot jj+1 of wave 0
+                int qn = -1;
+                if (j + 1 < m) {
+                    if (o + 1 < NW) {
+                        if (w == o + 1) {
+                            qn = 0;
+                            update(0);
+                            reflector(std::integral_constant<int, jj>{}, j + 1);
+                        }
+                    } else if constexpr (jj + 1 < MW) {
+                        if (w == 0) {
+                            qn = 1;
+                            update(1);
+                            reflector(std::integral_constant<int, jj + 1>{}, j + 1);
+                        }
                     }
                 }
+#pragma unroll
+                for (int q = 0; q < NT; ++q)
+                    if ((q > 0 || first) && q != qn) update(q);
             }
         });
-        // the first column of the next tile reuses buffer 0
+        // the first reflector of the next tile reuses buffer 0
         __syncthreads();
     }
     if (lane < m) {
@@ -352,22 +385,47 @@ __global__ __launch_bounds__(kColsThreads) void tsqr_cols_kernel(
 namespace {
 
 constexpr int64_t kMaxWaveSlices = 2048;  // single-wave slices: 256 CUs x 8 waves
-constexpr int64_t kMaxCoopSlices = 512;   // 4-wave slices: 2 per CU
+constexpr int64_t kMaxCoopSlices = 512;   // cooperative slices: up to 2 per CU
 constexpr int64_t kMaxColsSlices = 256;   // 256-thread slices: 1 per CU
-constexpr int kCoopWaves = 4;
 
 // Kernel family and shape for m columns.
 enum class Kind { Rows, Coop, Cols };
 struct Shape {
     Kind kind;
     int M;       // column bucket (Rows, Coop)
+    int nw;      // waves per workgroup (Coop)
     int rpt;     // rows per lane per tile (Rows, Coop)
     int cpt;     // columns per thread (Cols)
     int64_t tile;
 };
 
+// Cooperative-kernel configurations per column bucket: waves per workgroup
+// and rows per lane.  Entry 0 is the default; TTSVD_COOP_VARIANT selects
+// another one (a tuning override, the result does not depend on it beyond
+// the summation order).
+struct CoopCfg {
+    int nw, rpt;
+};
+constexpr CoopCfg kCoop16[3] = {{4, 16}, {8, 16}, {16, 16}};
+constexpr CoopCfg kCoop32[3] = {{4, 8}, {8, 16}, {16, 8}};
+constexpr CoopCfg kCoop64[3] = {{8, 8}, {4, 4}, {16, 4}};
+
+int coop_variant() {
+    static int v = [] {
+        const char *e = getenv("TTSVD_COOP_VARIANT");
+        int x = e ? atoi(e) : 0;
+        return (x >= 0 && x < 3) ? x : 0;
+    }();
+    return v;
+}
+
+CoopCfg coop_cfg(int M) {
+    const int v = coop_variant();
+    return M == 16 ? kCoop16[v] : M == 32 ? kCoop32[v] : kCoop64[v];
+}
+
 Shape shape_for(int64_t m) {
-    Shape sh{Kind::Cols, 0, 0, 0, 0};
+    Shape sh{Kind::Cols, 0, 0, 0, 0, 0};
     if (m <= 8) {
         sh.kind = Kind::Rows;
         sh.M = (int)cpow2((int)m);
@@ -376,7 +434,9 @@ Shape shape_for(int64_t m) {
     } else if (m <= 64) {
         sh.kind = Kind::Coop;
         sh.M = (int)cpow2((int)m);
-        sh.rpt = sh.M == 16 ? 16 : sh.M == 32 ? 8 : 4;
+        const CoopCfg c = coop_cfg(sh.M);
+        sh.nw = c.nw;
+        sh.rpt = c.rpt;
         sh.tile = (int64_t)kWave * sh.rpt;
     } else {
         sh.cpt = m <= 256 ? 1 : m <= 512 ? 2 : 4;
@@ -438,7 +498,7 @@ int launch_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level 
     if (sh.kind == Kind::Rows)
         snprintf(name, sizeof(name), "tsqr_rows_kernel<%d, %d, %s>", sh.M, sh.rpt, tname<Tin>());
     else if (sh.kind == Kind::Coop)
-        snprintf(name, sizeof(name), "tsqr_coop_kernel<%d, %d, %d, %s>", sh.M, kCoopWaves, sh.rpt,
+        snprintf(name, sizeof(name), "tsqr_coop_kernel<%d, %d, %d, %s>", sh.M, sh.nw, sh.rpt,
                  tname<Tin>());
     else
         snprintf(name, sizeof(name), "tsqr_cols_kernel<%d, %d, %s>", sh.cpt, 64 / sh.cpt, tname<Tin>());
@@ -471,20 +531,27 @@ int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Le
         }
 #undef TTSVD_ROWS_CASE
     } else if (sh.kind == Kind::Coop) {
-        dim3 grid((unsigned)l.nslices), block(kCoopWaves * kWave);
-#define TTSVD_COOP_CASE(MM, RR)                                                                 \
-    case MM:                                                                                    \
-        hipLaunchKernelGGL((tsqr_coop_kernel<MM, kCoopWaves, RR, Tin>), grid, block, 0, s, W,   \
-                           rows, (int)m, ld, l.rows_per_slice, l.nslices, out, ld_out,          \
-                           out_stride, kvalid);                                                 \
+        dim3 grid((unsigned)l.nslices), block(sh.nw * kWave);
+#define TTSVD_COOP_LAUNCH(MM, NN, RR)                                                         \
+    hipLaunchKernelGGL((tsqr_coop_kernel<MM, NN, RR, Tin>), grid, block, 0, s, W, rows, (int)m, \
+                       ld, l.rows_per_slice, l.nslices, out, ld_out, out_stride, kvalid)
+#define TTSVD_COOP_CASE(MM, TABLE)                                                             \
+    case MM:                                                                                  \
+        if (sh.nw == TABLE[0].nw && sh.rpt == TABLE[0].rpt)                                    \
+            TTSVD_COOP_LAUNCH(MM, TABLE[0].nw, TABLE[0].rpt);                                  \
+        else if (sh.nw == TABLE[1].nw && sh.rpt == TABLE[1].rpt)                               \
+            TTSVD_COOP_LAUNCH(MM, TABLE[1].nw, TABLE[1].rpt);                                  \
+        else                                                                                  \
+            TTSVD_COOP_LAUNCH(MM, TABLE[2].nw, TABLE[2].rpt);                                  \
         break;
         switch (sh.M) {
-            TTSVD_COOP_CASE(16, 16)
-            TTSVD_COOP_CASE(32, 8)
-            TTSVD_COOP_CASE(64, 4)
+            TTSVD_COOP_CASE(16, kCoop16)
+            TTSVD_COOP_CASE(32, kCoop32)
+            TTSVD_COOP_CASE(64, kCoop64)
             default:
                 return set_error(TTSVD_EUNSUPPORTED, "tsqr: bad column bucket %d", sh.M);
         }
+#undef TTSVD_COOP_LAUNCH
 #undef TTSVD_COOP_CASE
     } else {
         dim3 grid((unsigned)l.nslices), block(kColsThreads);
