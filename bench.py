@@ -115,7 +115,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--r-max", type=int, default=32)
     ap.add_argument("--workloads", default="d28n2,d7n16")
-    ap.add_argument("--cpu-sample-d", type=int, default=24)
+    ap.add_argument("--cpu-sample-d", type=int, default=27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
