@@ -23,6 +23,8 @@
 
 #include <cmath>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
@@ -250,106 +252,166 @@ __global__ __launch_bounds__(MB / 2 * LPP) void svd_small_kernel(
                      st, st0);
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void svd_jacobi_kernel(
-    const double *__restrict__ R, int64_t ldr, int K, int m, int lda, int use_lds,
-    double *__restrict__ gA, double *__restrict__ sigma_out, double *__restrict__ core_out,
-    int64_t r_max, double tol, int dm1, int first, StepState *st, StepState *st0) {
-    extern __shared__ double smem[];
-    __shared__ int rot_count;
+// ----------------------------------------------------------------------------
+// Large-matrix path (m > 64): block one-sided Jacobi over many workgroups.
+//
+// The K rows of R (zero-padded to Kp, a multiple of 2B) are split into nb
+// blocks of B rows in a global buffer.  A sweep is a round-robin tournament
+// over the blocks (nb - 1 block rounds); in each block round workgroup g
+// takes block pair g, copies its 2B rows to LDS, runs one full inner Jacobi
+// sweep over them (2B - 1 rounds of B parallel pairs, TPP lanes per pair)
+// and writes them back.  Block rounds are separated by a grid barrier of the
+// cooperative launch; a sweep in which no rotation had a relative
+// off-diagonal above 1e-9 is the last one (quadratic convergence).
+// ----------------------------------------------------------------------------
+constexpr int kBlockThreads = 256;
+constexpr int kBlockMaxE = 16;  // elements per lane and vector
+
+struct BlockCtl {
+    int big[kMaxSweeps];  // per sweep: workgroups that made a large rotation
+    int sweeps;           // sweeps performed
+};
+
+template <int B>
+__global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(
+    const double *__restrict__ R, int64_t ldr, int K, int m, int mp, int nb,
+    double *__restrict__ A, BlockCtl *ctl) {
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    constexpr int TPP = kBlockThreads / B;  // lanes per pair
+    extern __shared__ __attribute__((aligned(16))) double S[];  // 2B rows of mp
     const int tid = threadIdx.x;
-    const int kp = K + (K & 1);
-    double *A = use_lds ? smem : gA;                         // A[v*lda + e]
-    double *sig = use_lds ? smem + (int64_t)kp * lda : smem;  // K values
-    int *order = (int *)(sig + K);                             // K values
+    const int kp = nb * B;
+    const int ne = mp / TPP;  // elements per lane (even, <= kBlockMaxE)
 
-    for (int64_t idx = tid; idx < (int64_t)kp * m; idx += NT) {
-        const int v = (int)(idx / m), e = (int)(idx % m);
-        A[(int64_t)v * lda + e] = (v < K) ? R[v + ldr * e] : 0.0;
+    // rows of R -> A (zero padding beyond K rows and m columns)
+    for (int64_t idx = (int64_t)blockIdx.x * kBlockThreads + tid; idx < (int64_t)kp * mp;
+         idx += (int64_t)gridDim.x * kBlockThreads) {
+        const int vv = (int)(idx / mp), e = (int)(idx % mp);
+        A[idx] = (vv < K && e < m) ? R[vv + ldr * e] : 0.0;
     }
-    __syncthreads();
+    // One counter per sweep, zeroed before the first grid barrier and never
+    // reused, so every workgroup reads the same final count for its decision.
+    if (blockIdx.x == 0 && tid < kMaxSweeps) ctl->big[tid] = 0;
+    grid.sync();
 
-    const int npairs = kp / 2;
-    int tpp = 64;
-    while (tpp > 1 && tpp * npairs > NT) tpp >>= 1;  // lanes per pair
-    const int groups = NT / tpp;
-    const int sub = tid % tpp;
-    // Rotate while |a_p^T a_q| > 4 m eps ||a_p|| ||a_q||: above the rounding
-    // floor of the computed dot products, so the sweeps terminate, and tight
-    // enough that the normalised rows are orthogonal to ~1e-13.
+    const int pi = tid / TPP;
+    const int sub = tid % TPP;
     const double thr = 4.0 * (double)m * 0x1p-52;
+    const double thr2 = thr * thr;
+    __shared__ int big_wg;
 
     int sweep = 0;
     for (; sweep < kMaxSweeps; ++sweep) {
-        if (tid == 0) rot_count = 0;
-        __syncthreads();
-        int local = 0;
-        for (int round = 0; round < kp - 1; ++round) {
-            for (int pb = 0; pb < npairs; pb += groups) {
-                const int pi = pb + tid / tpp;
-                if (pi < npairs) {
-                    int p, q;
-                    pair_of(round, pi, kp, p, q);
-                    double *ap = A + (int64_t)p * lda, *aq = A + (int64_t)q * lda;
-                    double al = 0.0, be = 0.0, ga = 0.0;
-                    for (int e = sub; e < m; e += tpp) {
-                        const double x = ap[e], y = aq[e];
-                        al = fma(x, x, al);
-                        be = fma(y, y, be);
-                        ga = fma(x, y, ga);
-                    }
-                    for (int d = tpp >> 1; d >= 1; d >>= 1) {
-                        al += __shfl_xor(al, d, kWave);
-                        be += __shfl_xor(be, d, kWave);
-                        ga += __shfl_xor(ga, d, kWave);
-                    }
-                    if (p < K && q < K && al > 0.0 && be > 0.0 &&
-                        fabs(ga) > thr * std::sqrt(al) * std::sqrt(be)) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        double t;
-                        if (fabs(zeta) > 1e150)
-                            t = 0.5 / zeta;
-                        else
-                            t = copysign(1.0, zeta) / (fabs(zeta) + std::sqrt(fma(zeta, zeta, 1.0)));
-                        const double c = 1.0 / std::sqrt(fma(t, t, 1.0));
-                        const double s = c * t;
-                        for (int e = sub; e < m; e += tpp) {
-                            const double x = ap[e], y = aq[e];
-                            ap[e] = fma(c, x, -s * y);
-                            aq[e] = fma(s, x, c * y);
-                        }
-                        if (sub == 0) ++local;
-                    }
-                }
+        if (tid == 0) big_wg = 0;
+        bool big = false;
+        for (int br = 0; br < nb - 1; ++br) {
+            int bp, bq;
+            pair_of(br, blockIdx.x, nb, bp, bq);
+            for (int idx = tid; idx < B * mp; idx += kBlockThreads) {
+                const int vv = idx / mp, e = idx % mp;
+                S[vv * mp + e] = A[(int64_t)(bp * B + vv) * mp + e];
+                S[(B + vv) * mp + e] = A[(int64_t)(bq * B + vv) * mp + e];
             }
             __syncthreads();
+            for (int round = 0; round < 2 * B - 1; ++round) {
+                int p, q;
+                pair_of(round, pi, 2 * B, p, q);
+                double *ap = S + p * mp + 2 * sub;
+                double *aq = S + q * mp + 2 * sub;
+                double x[kBlockMaxE], y[kBlockMaxE];
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int e = 0; e < kBlockMaxE; ++e) {
+                    if (e < ne) {
+                        x[e] = ap[2 * TPP * (e / 2) + (e & 1)];
+                        y[e] = aq[2 * TPP * (e / 2) + (e & 1)];
+                        al = fma(x[e], x[e], al);
+                        be = fma(y[e], y[e], be);
+                        ga = fma(x[e], y[e], ga);
+                    }
+                }
+                al = group_sum<TPP>(al);
+                be = group_sum<TPP>(be);
+                ga = group_sum<TPP>(ga);
+                const double g2a = ga * ga;
+                if (g2a > thr2 * al * be && al > kTinyNorm2 && be > kTinyNorm2) {
+                    const double dlt = be - al;
+                    const double g2 = ga + ga;
+                    const double h = fma(dlt, dlt, g2 * g2);
+                    const double den = fabs(dlt) + h * rsqrt_nr(h);
+                    const double t = (dlt < 0.0 ? -g2 : g2) * rcp_nr(den);
+                    const double c = rsqrt_nr(fma(t, t, 1.0));
+                    const double s = c * t;
+                    big |= g2a > kBigRel2 * al * be;
+#pragma unroll
+                    for (int e = 0; e < kBlockMaxE; ++e) {
+                        if (e < ne) {
+                            ap[2 * TPP * (e / 2) + (e & 1)] = fma(c, x[e], -s * y[e]);
+                            aq[2 * TPP * (e / 2) + (e & 1)] = fma(s, x[e], c * y[e]);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            for (int idx = tid; idx < B * mp; idx += kBlockThreads) {
+                const int vv = idx / mp, e = idx % mp;
+                A[(int64_t)(bp * B + vv) * mp + e] = S[vv * mp + e];
+                A[(int64_t)(bq * B + vv) * mp + e] = S[(B + vv) * mp + e];
+            }
+            grid.sync();
         }
-        if (local) atomicAdd(&rot_count, local);
+        if (big) big_wg = 1;
         __syncthreads();
-        const int rc = rot_count;
+        if (tid == 0 && big_wg) atomicAdd(&ctl->big[sweep], 1);
+        grid.sync();
+        const int nbig = __atomic_load_n(&ctl->big[sweep], __ATOMIC_RELAXED);
+        if (nbig == 0) {
+            ++sweep;
+            break;
+        }
         __syncthreads();
-        if (rc == 0) break;
     }
+    if (blockIdx.x == 0 && tid == 0) ctl->sweeps = sweep;
+}
 
-    svd_epilogue<NT>(A, lda, K, m, sig, order, sigma_out, core_out, r_max, tol, dm1, first, sweep,
-                     st, st0);
+// Singular values, truncation and core of the rotated rows A (kp x mp).
+__global__ __launch_bounds__(1024) void svd_block_finish_kernel(
+    const double *__restrict__ A, int K, int m, int mp, const BlockCtl *ctl,
+    double *__restrict__ sigma_out, double *__restrict__ core_out, int64_t r_max, double tol,
+    int dm1, int first, StepState *st, StepState *st0) {
+    extern __shared__ double smem[];
+    double *sig = smem;
+    int *order = (int *)(sig + K);
+    svd_epilogue<1024>(A, mp, K, m, sig, order, sigma_out, core_out, r_max, tol, dm1, first,
+                       ctl->sweeps, st, st0);
 }
 
 namespace {
-constexpr size_t kLdsBudget = 60 * 1024;
 
-int lda_for(int64_t m) { return (int)(m + ((m % 32) == 0 ? 1 : 0)); }
-
-bool fits_lds(int64_t K, int64_t m) {
-    const int64_t kp = K + (K & 1);
-    return (size_t)(kp * lda_for(m)) * 8 + (size_t)K * 12 <= kLdsBudget;
+// Block shape of the large-matrix path: B rows per block with 2 B rows of
+// mp (m rounded up to 2 TPP) in at most 64 KiB of LDS, TPP = 256 / B.
+struct BlockShape {
+    int B, tpp, mp, nb, kp;
+};
+BlockShape block_shape(int64_t K, int64_t m) {
+    BlockShape b{32, 0, 0, 0, 0};
+    for (;;) {
+        b.tpp = kBlockThreads / b.B;
+        b.mp = (int)ceil_div(m, 2 * b.tpp) * 2 * b.tpp;
+        if ((int64_t)2 * b.B * b.mp * 8 <= 64 * 1024 || b.B == 4) break;
+        b.B /= 2;
+    }
+    b.nb = (int)ceil_div(K, 2 * b.B) * 2;
+    b.kp = b.nb * b.B;
+    return b;
 }
 }  // namespace
 
 size_t svd_scratch_bytes(int64_t K, int64_t m) {
-    if (fits_lds(K, m)) return 0;
-    const int64_t kp = K + (K & 1);
-    return (size_t)(kp * lda_for(m)) * sizeof(double);
+    if (m <= 64) return 0;
+    const BlockShape b = block_shape(K, m);
+    return (size_t)b.kp * b.mp * sizeof(double) + sizeof(BlockCtl) + 256;
 }
 
 // Lanes per Jacobi pair of the small-matrix kernel (TTSVD_SVD_LPP = 8 or 16,
@@ -367,11 +429,6 @@ int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma
                StepState *state, StepState *state0, void *scratch, hipStream_t s) {
     if (K < 1 || m < 1 || K > m || m > 4096)
         return set_error(TTSVD_EINVAL, "svd: bad shape K=%lld m=%lld", (long long)K, (long long)m);
-    const bool lds = fits_lds(K, m);
-    const int lda = lda_for(m);
-    const int64_t kp = K + (K & 1);
-    size_t shmem = (size_t)K * 12 + 16;
-    if (lds) shmem += (size_t)(kp * lda) * 8;
     if (m <= 64) {
         const int MB = m <= 16 ? 16 : m <= 32 ? 32 : 64;
         const int lpp = MB == 16 ? 8 : svd_lpp();
@@ -396,17 +453,39 @@ int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma
         TTSVD_HIP_TRY(hipGetLastError());
         return TTSVD_OK;
     }
-    prof_begin(s, K <= 64 ? "svd_jacobi_kernel<256>" : "svd_jacobi_kernel<1024>",
-               (double)(m * m) * 8.0 + (double)(K * m) * 8.0, 0.0);
-    if (K <= 64) {
-        hipLaunchKernelGGL(svd_jacobi_kernel<256>, dim3(1), dim3(256), shmem, s, R, ldr, (int)K,
-                           (int)m, lda, (int)lds, (double *)scratch, sigma_out, core_out, r_max,
-                           tol, dm1, first, state, state0);
-    } else {
-        hipLaunchKernelGGL(svd_jacobi_kernel<1024>, dim3(1), dim3(1024), shmem, s, R, ldr, (int)K,
-                           (int)m, lda, (int)lds, (double *)scratch, sigma_out, core_out, r_max,
-                           tol, dm1, first, state, state0);
+    if (m > 1024)
+        return set_error(TTSVD_EUNSUPPORTED, "svd: m = %lld > 1024", (long long)m);
+    const BlockShape b = block_shape(K, m);
+    if (b.mp / b.tpp > kBlockMaxE)
+        return set_error(TTSVD_EUNSUPPORTED, "svd: block shape for m = %lld", (long long)m);
+    double *A = (double *)scratch;
+    BlockCtl *ctl = (BlockCtl *)(A + (size_t)b.kp * b.mp);
+    char name[64];
+    snprintf(name, sizeof(name), "svd_block_kernel<%d>", b.B);
+    prof_begin(s, name, (double)(m * m) * 8.0 + (double)(K * m) * 8.0, 0.0);
+    const size_t lds = (size_t)2 * b.B * b.mp * sizeof(double);
+    int nbk = b.nb / 2;
+    void *args[] = {(void *)&R, (void *)&ldr, (void *)&K, (void *)&m, (void *)&b.mp,
+                    (void *)&b.nb, (void *)&A, (void *)&ctl};
+    int Ki = (int)K, mi = (int)m, mpi = b.mp, nbi = b.nb;
+    args[2] = &Ki;
+    args[3] = &mi;
+    args[4] = &mpi;
+    args[5] = &nbi;
+    hipError_t e;
+    switch (b.B) {
+        case 32: e = hipLaunchCooperativeKernel((const void *)svd_block_kernel<32>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
+        case 16: e = hipLaunchCooperativeKernel((const void *)svd_block_kernel<16>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
+        case 8: e = hipLaunchCooperativeKernel((const void *)svd_block_kernel<8>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
+        default: e = hipLaunchCooperativeKernel((const void *)svd_block_kernel<4>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
     }
+    prof_end(s);
+    if (e != hipSuccess)
+        return set_error(TTSVD_EHIP, "svd: cooperative launch: %s", hipGetErrorString(e));
+    prof_begin(s, "svd_block_finish_kernel", (double)(K * m) * 8.0, 0.0);
+    hipLaunchKernelGGL(svd_block_finish_kernel, dim3(1), dim3(1024), (size_t)K * 12 + 16, s, A,
+                       (int)K, (int)m, b.mp, ctl, sigma_out, core_out, r_max, tol, dm1, first,
+                       state, state0);
     prof_end(s);
     TTSVD_HIP_TRY(hipGetLastError());
     return TTSVD_OK;

@@ -176,6 +176,7 @@ def test_small_exact_tt_workload():
 @pytest.mark.parametrize("dims,r_max,tol", [
     ([2] * 12, 5, 0.0), ([2] * 12, 16, 0.0), ([3, 4, 5, 6], 4, 0.0), ([16, 16, 16], 7, 0.0),
     ([4] * 7, 10, 0.0), ([2] * 14, 32, 0.0), ([8, 8, 8, 8], 100, 0.0),
+    ([16, 16, 16, 16], 40, 0.0), ([8, 8, 8, 8, 8], 24, 0.0),
 ])
 def test_uniform_tensors_match_oracle(dims, r_max, tol):
     log("uniform %s r=%d" % (dims, r_max))
