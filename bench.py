@@ -89,6 +89,45 @@ def roofline_of(stats):
     return roof
 
 
+def precision_forms(tt, X64, dims, r_max, steps, warmup, f64_sec, f64_res):
+    """FP32 / BF16 storage forms of the same workload: speed at full size and
+    accuracy (singular values against the FP64 run; reconstruction of a 2^20
+    exact TT + 1e-4 noise tensor against the FP64 oracle)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2102_00104_amd import model, synth
+    out = {}
+    dsmall = [2] * 20
+    Xs = synth.exact_tt(dsmall, 16, seed=61, noise=1e-4, noise_seed=62, unit_variance=True,
+                        relative_noise=True)
+    o = oracle.ttsvd(Xs, dsmall, r_max, 0.0)
+    e_or = oracle.rel_error(Xs, oracle.tt_full(o.cores))
+    for name, dt, eb in (("f32", torch.float32, 4), ("bf16", torch.bfloat16, 2)):
+        Xl = X64.to(dt)
+        sec, res = time_decompose(tt, Xl, dims, r_max, 0.0, steps, warmup)
+        dev = 0.0
+        for j in range(1, len(dims)):
+            a, b = np.asarray(res.sigma[j]), np.asarray(f64_res.sigma[j])
+            r = f64_res.ranks[j]
+            dev = max(dev, float(np.max(np.abs(a[:r] - b[:r])) / b[0]))
+        g = tt.ttsvd_decompose(torch.from_numpy(Xs).to(X64.device).to(dt), dsmall, r_max, 0.0)
+        cores = [tt.core_array(c, (g.ranks[j], dsmall[j], g.ranks[j + 1]))
+                 for j, c in enumerate(g.cores)]
+        e = oracle.rel_error(Xs, oracle.tt_full(cores))
+        ab = model.algorithmic_bytes(dims, f64_res.ranks, eb)
+        out[name] = {"value": round(ab / sec / 1e9, 2), "unit": "GB/s",
+                     "ms_per_step": round(sec * 1e3, 3),
+                     "speedup_vs_f64": round(f64_sec / sec, 3),
+                     "max_kept_sigma_dev_vs_f64_rel_sigma1": dev,
+                     "exact_tt_2e20_rel_error": e, "exact_tt_2e20_rel_error_fp64_oracle": e_or}
+        log("%s: %.3f ms/step (%.2fx FP64), sigma dev %.2e, rel. error %.3e (oracle %.3e)" % (
+            name, sec * 1e3, f64_sec / sec, dev, e, e_or))
+        del Xl
+    return out
+
+
 def cpu_baseline(d_sample, r_max):
     """The CPU FP64 oracle on a bounded sample of the same workload."""
     import numpy as np
@@ -115,8 +154,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--r-max", type=int, default=32)
     ap.add_argument("--workloads", default="d28n2,d7n16")
-    ap.add_argument("--cpu-sample-d", type=int, default=27)
+    ap.add_argument("--cpu-sample-d", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (row slabs of the "
@@ -154,7 +194,7 @@ def main():
                 s["flops"] / (s["total_ms"] / 1e3) / 1e12 if s["total_ms"] else 0))
         results.append(dict(workload=wname, dims=dims, ranks=ranks, ms_per_step=sec * 1e3,
                             value=abytes / sec / 1e9, bytes=abytes, flops=aflops,
-                            roofline=roofline_of(stats), kernels=stats))
+                            roofline=roofline_of(stats), kernels=stats, sec=sec, res=res))
 
     head = results[0]
     line = {
@@ -181,6 +221,9 @@ def main():
                     "hbm_roofline_frac": round(r["value"] / HBM_PEAK_GBS, 4),
                     "roofline": r["roofline"]} for r in results[1:]],
     }
+    if not args.no_precision:
+        line["precision_forms"] = precision_forms(tt, X, head["dims"], args.r_max, args.steps,
+                                                  args.warmup, head["sec"], head["res"])
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a 2^%d sample" % args.cpu_sample_d)
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_d, args.r_max)
