@@ -153,7 +153,65 @@ typedef struct ttsvd_tt {
 int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d,
                     int64_t r_max, double tol, ttsvd_tt *out);
 
-/* Release the buffers of a ttsvd_tt filled by ttsvd_decompose (NULL-safe). */
+/*
+ * Batched form: Algorithm 2 applied independently to `count` tensors of
+ * different shapes in one persistent cooperative launch.  All tensors advance
+ * one TT step per round; the phases of a round (TSQR tree levels, small SVD
+ * with truncation, TSMM + reshape) run the work units of every tensor over the
+ * whole GPU, and each tensor's rank decision stays on the device.
+ */
+typedef struct ttsvd_batch_config {
+    int grid;        /* workgroups of the persistent launch; 0 = all co-resident ones */
+    int tile_set;    /* register tiling of the TSQR bodies (0)                      */
+    int min_tiles;   /* a TSQR slice spans at least this many row tiles (>= 1)      */
+    int max_slices;  /* TSQR slices per tensor and tree level at most (>= 1)        */
+} ttsvd_batch_config;
+
+/* The configuration used when no tuned one is known; returns TTSVD_OK. */
+int ttsvd_batch_default_config(ttsvd_batch_config *cfg);
+
+/*
+ * ttsvd_decompose_batch -- TT decomposition of count tensors (Algorithm 2).
+ *
+ *   count  number of tensors, 1 <= count <= 4096.
+ *   X      count input tensors (device, read only), all of the same dtype;
+ *          X[t].stream is ignored.
+ *   d      count mode counts (host), 1 <= d[t] <= TTSVD_MAX_D.
+ *   dims   the dims of all tensors concatenated (host, sum of d[t] values).
+ *   r_max  count maximal ranks (host, >= 1);  tol: count tolerances (host,
+ *          >= 0), both as in ttsvd_decompose.
+ *   cfg    tuning knobs, or NULL for the configuration ttsvd_batch_autotune
+ *          found for this exact batch in this process (else the default).
+ *   stream stream all work is enqueued on; synchronised before returning.
+ *   out    count results, each released with ttsvd_tt_free (the cores of
+ *          one call share a device allocation that the last free releases).
+ *
+ * Every step of every tensor must have at most 128 columns (n_j r_j <= 128
+ * for the rank upper bounds min(r_max, ...)); larger problems belong to
+ * ttsvd_decompose.  Errors: TTSVD_EINVAL, TTSVD_EUNSUPPORTED (mixed dtypes,
+ * more than 128 columns), TTSVD_ENOMEM, TTSVD_EHIP, TTSVD_ENONFINITE (then
+ * no result is returned).
+ */
+int ttsvd_decompose_batch(int count, const ttsvd_tensor *X, const int *d,
+                          const int64_t *dims, const int64_t *r_max,
+                          const double *tol, const ttsvd_batch_config *cfg,
+                          hipStream_t stream, ttsvd_tt *out);
+
+/*
+ * ttsvd_batch_autotune -- time the batch under each candidate configuration
+ * (TSQR slice sizes and counts, tile sets), return the fastest in *best and
+ * its time in *best_ms (may be NULL), and remember it for later
+ * ttsvd_decompose_batch calls with cfg = NULL on the same batch (same count,
+ * dtype, dims, r_max, tol and strides).  The decompositions it runs are
+ * discarded.  Errors as ttsvd_decompose_batch.
+ */
+int ttsvd_batch_autotune(int count, const ttsvd_tensor *X, const int *d,
+                         const int64_t *dims, const int64_t *r_max,
+                         const double *tol, hipStream_t stream,
+                         ttsvd_batch_config *best, double *best_ms);
+
+/* Release the buffers of a ttsvd_tt filled by ttsvd_decompose or
+ * ttsvd_decompose_batch (NULL-safe). */
 void ttsvd_tt_free(ttsvd_tt *tt);
 
 /* Device bytes ttsvd_decompose allocates for this problem (work matrices,

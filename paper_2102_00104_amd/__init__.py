@@ -29,7 +29,8 @@ ERRORS = {-1: "TTSVD_EINVAL", -2: "TTSVD_ENOMEM", -3: "TTSVD_EHIP",
 EXPORTED = ["ttsvd_tsqr_r", "ttsvd_tsqr_workspace_size", "ttsvd_gemm_reshape",
             "ttsvd_decompose", "ttsvd_tt_free", "ttsvd_footprint_bytes",
             "ttsvd_strerror", "ttsvd_last_error", "ttsvd_version",
-            "ttsvd_profile_enable", "ttsvd_profile_reset", "ttsvd_profile_read"]
+            "ttsvd_profile_enable", "ttsvd_profile_reset", "ttsvd_profile_read",
+            "ttsvd_batch_default_config", "ttsvd_decompose_batch", "ttsvd_batch_autotune"]
 
 
 class TTSVDError(RuntimeError):
@@ -76,6 +77,19 @@ class TensorStruct(ctypes.Structure):
     ]
 
 
+class BatchConfig(ctypes.Structure):
+    """ctypes mirror of ``ttsvd_batch_config``."""
+    _fields_ = [
+        ("grid", ctypes.c_int),
+        ("tile_set", ctypes.c_int),
+        ("min_tiles", ctypes.c_int),
+        ("max_slices", ctypes.c_int),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 _lib = None
 _hip = None
 
@@ -116,6 +130,17 @@ def lib() -> ctypes.CDLL:
         L.ttsvd_profile_read.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]
         L.ttsvd_profile_read.restype = ctypes.c_int
+        L.ttsvd_batch_default_config.argtypes = [ctypes.POINTER(BatchConfig)]
+        L.ttsvd_batch_default_config.restype = ctypes.c_int
+        L.ttsvd_decompose_batch.argtypes = [
+            ctypes.c_int, ctypes.POINTER(TensorStruct), ctypes.POINTER(ctypes.c_int),
+            ctypes.POINTER(i64), ctypes.POINTER(i64), dp, ctypes.POINTER(BatchConfig), vp,
+            ctypes.POINTER(TTStruct)]
+        L.ttsvd_decompose_batch.restype = ctypes.c_int
+        L.ttsvd_batch_autotune.argtypes = [
+            ctypes.c_int, ctypes.POINTER(TensorStruct), ctypes.POINTER(ctypes.c_int),
+            ctypes.POINTER(i64), ctypes.POINTER(i64), dp, vp, ctypes.POINTER(BatchConfig), dp]
+        L.ttsvd_batch_autotune.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -208,10 +233,32 @@ class TT:
     err_bound: float
 
 
+def _to_tt(out: TTStruct, device, st: int, fetch: bool = True) -> TT:
+    """Copy a filled ``ttsvd_tt`` into a TT (cores only if fetch)."""
+    import torch
+    d = int(out.d)
+    dims = [int(out.dims[j]) for j in range(d)]
+    ranks = [int(out.ranks[i]) for i in range(d + 1)]
+    cores = []
+    if fetch:
+        for j in range(d):
+            n = ranks[j] * dims[j] * ranks[j + 1]
+            t = torch.empty(n, dtype=torch.float64, device=device)
+            rc = _hiprt().hipMemcpyAsync(t.data_ptr(), out.cores[j], n * 8, 3, st)
+            if rc != 0:
+                raise RuntimeError("hipMemcpyAsync failed: %d" % rc)
+            cores.append(t)
+        torch.cuda.synchronize(device)
+    sigma = [None] * d
+    for j in range(1, d):
+        sigma[j] = [out.sigma[j][i] for i in range(int(out.nsigma[j]))]
+    return TT(dims, ranks, cores, sigma, [float(out.discarded2[j]) for j in range(d)],
+              float(out.delta), float(out.norm_sigma), float(out.err_bound))
+
+
 def ttsvd_decompose(X, dims: Sequence[int], r_max: int, tol: float, ld_last: int = 0,
                     stream=None) -> TT:
     """``ttsvd_decompose`` of the Fortran-ordered device tensor X (flat storage)."""
-    import torch
     dims = [int(n) for n in dims]
     d = len(dims)
     st = _stream(stream)
@@ -220,24 +267,58 @@ def ttsvd_decompose(X, dims: Sequence[int], r_max: int, tol: float, ld_last: int
     out = TTStruct()
     _check(lib().ttsvd_decompose(ctypes.byref(xs), arr, d, r_max, float(tol), ctypes.byref(out)))
     try:
-        ranks = [int(out.ranks[i]) for i in range(d + 1)]
-        cores = []
-        for j in range(d):
-            shape = (ranks[j], dims[j], ranks[j + 1])
-            n = shape[0] * shape[1] * shape[2]
-            t = torch.empty(n, dtype=torch.float64, device=X.device)
-            rc = _hiprt().hipMemcpyAsync(t.data_ptr(), out.cores[j], n * 8, 3, st)
-            if rc != 0:
-                raise RuntimeError("hipMemcpyAsync failed: %d" % rc)
-            cores.append(t)
-        torch.cuda.synchronize(X.device)
-        sigma = [None] * d
-        for j in range(1, d):
-            sigma[j] = [out.sigma[j][i] for i in range(int(out.nsigma[j]))]
-        return TT(dims, ranks, cores, sigma, [float(out.discarded2[j]) for j in range(d)],
-                  float(out.delta), float(out.norm_sigma), float(out.err_bound))
+        return _to_tt(out, X.device, st)
     finally:
         lib().ttsvd_tt_free(ctypes.byref(out))
+
+
+def _batch_args(Xs, dims_list, r_max, tol, st):
+    n = len(Xs)
+    if n != len(dims_list):
+        raise ValueError("one dims list per tensor")
+    r_max = list(r_max) if isinstance(r_max, (list, tuple)) else [int(r_max)] * n
+    tol = list(tol) if isinstance(tol, (list, tuple)) else [float(tol)] * n
+    xs = (TensorStruct * n)(*[TensorStruct(X.data_ptr(), dtype_code(X), 0, st) for X in Xs])
+    d = (ctypes.c_int * n)(*[len(dl) for dl in dims_list])
+    flat = [int(v) for dl in dims_list for v in dl]
+    dims = (ctypes.c_int64 * max(1, len(flat)))(*flat)
+    rm = (ctypes.c_int64 * n)(*[int(r) for r in r_max])
+    tl = (ctypes.c_double * n)(*[float(t) for t in tol])
+    return n, xs, d, dims, rm, tl
+
+
+def batch_default_config() -> BatchConfig:
+    c = BatchConfig()
+    _check(lib().ttsvd_batch_default_config(ctypes.byref(c)))
+    return c
+
+
+def ttsvd_decompose_batch(Xs, dims_list, r_max, tol, cfg: Optional[BatchConfig] = None,
+                          stream=None, fetch: bool = True) -> List[TT]:
+    """``ttsvd_decompose_batch`` of the Fortran-ordered device tensors Xs (one
+    persistent launch); r_max and tol are scalars or per-tensor lists.  With
+    fetch=False the cores are not copied out (ranks, sigma and bounds only)."""
+    st = _stream(stream)
+    n, xs, d, dims, rm, tl = _batch_args(Xs, dims_list, r_max, tol, st)
+    outs = (TTStruct * n)()
+    _check(lib().ttsvd_decompose_batch(n, xs, d, dims, rm, tl,
+                                       ctypes.byref(cfg) if cfg is not None else None, st, outs))
+    try:
+        return [_to_tt(outs[t], Xs[t].device, st, fetch) for t in range(n)]
+    finally:
+        for t in range(n):
+            lib().ttsvd_tt_free(ctypes.byref(outs[t]))
+
+
+def ttsvd_batch_autotune(Xs, dims_list, r_max, tol, stream=None):
+    """``ttsvd_batch_autotune``: (best BatchConfig, its time in ms)."""
+    st = _stream(stream)
+    n, xs, d, dims, rm, tl = _batch_args(Xs, dims_list, r_max, tol, st)
+    best = BatchConfig()
+    ms = ctypes.c_double(0.0)
+    _check(lib().ttsvd_batch_autotune(n, xs, d, dims, rm, tl, st, ctypes.byref(best),
+                                      ctypes.byref(ms)))
+    return best, float(ms.value)
 
 
 def core_array(t, shape):

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "common.h"
+#include "driver.h"
 #include "kernels.h"
 
 namespace ttsvd {
@@ -30,27 +31,16 @@ int set_error(int code, const char *fmt, ...) {
 
 void clear_error() { g_err[0] = 0; }
 
-namespace {
-
 bool valid_dtype(int dt) { return dt == TTSVD_F64 || dt == TTSVD_F32 || dt == TTSVD_BF16; }
 
+namespace {
 // Device state of one decomposition: per-step ranks and discarded energy plus
 // the threshold set by the first step.
 struct DecompState {
     StepState step[TTSVD_MAX_D];
     double one;  // 1.0, the 1 x 1 "V" used to copy a single-mode tensor
 };
-
-// Owner of the library-allocated outputs of ttsvd_decompose.
-struct TTPriv {
-    double *cores_dev = nullptr;
-    std::vector<double *> sigma_host;
-};
-
-// Shapes of every step for the rank upper bounds (the no-tolerance ranks).
-struct StepShape {
-    int64_t m, rows, K, rb;  // columns, rows, min(rows, m), rank bound
-};
+}  // namespace
 
 int plan_steps(const int64_t *dims, int d, int64_t r_max, std::vector<StepShape> &steps,
                std::vector<int64_t> &rb, int64_t &nbar_out) {
@@ -78,6 +68,7 @@ int plan_steps(const int64_t *dims, int d, int64_t r_max, std::vector<StepShape>
     return TTSVD_OK;
 }
 
+namespace {
 struct Footprint {
     size_t wbuf[2] = {0, 0};   // ping-pong work matrices (elements)
     size_t rbuf = 0;           // doubles
@@ -113,7 +104,7 @@ Footprint footprint(const int64_t *dims, int d, int dtype, const std::vector<Ste
     return f;
 }
 
-size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
 
 // Keep freed stream-ordered allocations in the device's default pool instead
 // of returning them to the driver at every synchronisation, so repeated
@@ -134,7 +125,6 @@ int keep_pool_memory(hipStream_t s) {
     return TTSVD_OK;
 }
 
-}  // namespace
 }  // namespace ttsvd
 
 using namespace ttsvd;
@@ -223,6 +213,10 @@ void ttsvd_tt_free(ttsvd_tt *tt) {
     TTPriv *p = (TTPriv *)tt->priv;
     if (p) {
         if (p->cores_dev) (void)hipFree(p->cores_dev);
+        if (p->shared && p->shared->refs.fetch_sub(1) == 1) {
+            (void)hipFree(p->shared->ptr);
+            delete p->shared;
+        }
         for (double *s : p->sigma_host) free(s);
         delete p;
     }

@@ -90,15 +90,25 @@ __device__ inline float dev_sqrt(float x) { return __builtin_sqrtf(x); }
 
 // ------------------------------------------------------- wave reductions
 
-__device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+// threadIdx.x behind an empty asm statement.  Values derived from it are
+// then computed where a body uses them instead of being hoisted to the start
+// of a persistent kernel, where those of every inlined body would be live at
+// once.  The statement emits no instruction.
+__device__ __forceinline__ int thread_id() {
+    int t = (int)threadIdx.x;
+    __asm__ volatile("" : "+v"(t));
+    return t;
+}
+
+__device__ inline int lane_id() { return thread_id() & (kWave - 1); }
 
 
-constexpr int cpow2(int n) {
+__host__ __device__ __forceinline__ constexpr int cpow2(int n) {
     int p = 1;
     while (p < n) p <<= 1;
     return p;
 }
-constexpr int clog2(int n) {
+__host__ __device__ __forceinline__ constexpr int clog2(int n) {
     int q = 0;
     while ((1 << q) < n) ++q;
     return q;

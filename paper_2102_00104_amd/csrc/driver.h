@@ -1,0 +1,46 @@
+// Host-side helpers shared by the single-tensor and the batched drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <vector>
+
+#include "ttsvd.h"
+
+namespace ttsvd {
+
+bool valid_dtype(int dt);
+
+__host__ __device__ constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Shapes of every step for the rank upper bounds (the no-tolerance ranks):
+// step i (1 <= i < d, 0-based mode index) has m = dims[i] rb[i+1] columns.
+struct StepShape {
+    int64_t m, rows, K, rb;  // columns, rows, min(rows, m), rank bound
+};
+
+// Fills steps[1..d-1] and the rank bounds rb[0..d]; validates dims.
+int plan_steps(const int64_t *dims, int d, int64_t r_max, std::vector<StepShape> &steps,
+               std::vector<int64_t> &rb, int64_t &nbar_out);
+
+// Keep freed stream-ordered allocations in the device's default pool.
+int keep_pool_memory(hipStream_t s);
+
+// Device buffer shared by the results of one batched call: the last
+// ttsvd_tt_free of those results releases it.
+struct SharedDev {
+    void *ptr = nullptr;
+    std::atomic<int> refs{0};
+};
+
+// Owner of the library-allocated outputs of one ttsvd_tt.
+struct TTPriv {
+    double *cores_dev = nullptr;   // own allocation (single-tensor path)
+    SharedDev *shared = nullptr;   // shared allocation (batched path)
+    std::vector<double *> sigma_host;
+};
+
+}  // namespace ttsvd

@@ -1,20 +1,14 @@
 // Rank-preserving Q-less TSQR (Sec. 3.2 of arXiv 2102.00104) for gfx950.
 //
 // The triangular factor R of a tall-skinny W is computed without forming Q:
-// each wave (m <= 64) or workgroup (m > 64) runs a flat reduction over a
+// each wave (m <= 8) or workgroup (m > 8) runs a flat reduction over a
 // contiguous slice of rows, applying the Householder step of Algorithm 6 to
 // [R; M] for every row tile M; the slices' triangular factors are stacked into
 // a (slices*m) x m matrix and reduced the same way, level by level, until one
 // slice remains.  The tree's shape depends only on (rows, m), so results are
 // deterministic.  W is never written.
 //
-// Householder step (Algorithm 6): for column j, the reflector acts on the
-// vector u = (R_jj ; M_{:,j}); with eps the smallest normalized number,
-//   t = ||u||^2 + eps,  alpha = -sign(u_1) sqrt(t + eps),
-//   t <- t - alpha u_1,  u_1 <- u_1 - alpha,  v = u / sqrt(t)   (||v||^2 = 2),
-// R_jj <- alpha, and every trailing column x = (R_jk ; M_{:,k}) becomes
-// x - (v^T x) v.  The eps terms keep the step free of branches and divisions
-// by zero for zero columns.
+// The Householder step and the device bodies are in tsqr_dev.h.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -24,259 +18,34 @@
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
+#include "tsqr_dev.h"
 
 namespace ttsvd {
 
-// ----------------------------------------------------------------------------
-// Row-owner wave kernel, m <= M <= 64.
-//
-// Lane l holds rows (tile_base + l + 64 i), i < RPT, of the current row tile
-// and row l of the wave's triangular factor, all in registers.  Column dot
-// products are reduced across the wave with wave_allreduce_vec.
-// ----------------------------------------------------------------------------
-constexpr int kRowsWaves = 4;  // waves (= slices) per workgroup
-
+// Per-level kernels of the single-tensor path: one workgroup per vblock.
 template <int M, int RPT, typename Tin>
 __global__ __launch_bounds__(kRowsWaves *kWave) void tsqr_rows_kernel(
     const Tin *__restrict__ W, int64_t rows, int m, int64_t ld,
     int64_t rows_per_slice, int64_t nslices, double *__restrict__ out,
     int64_t ld_out, int64_t out_row0_stride, int kvalid) {
-    using T = typename Elem<Tin>::acc;
-    constexpr int CH = (M < 16) ? M : 16;  // trailing columns per reduction
-    __shared__ T red[kRowsWaves][kWave];
-
-    const int lane = lane_id();
-    const int wid = threadIdx.x / kWave;
-    const int64_t slice = (int64_t)blockIdx.x * kRowsWaves + wid;
-    if (slice >= nslices) return;  // uniform per wave
-    const int64_t r0 = slice * rows_per_slice;
-    const int64_t r1 = min(rows, r0 + rows_per_slice);
-    T *lds = red[wid];
-    const T eps = EpsFP<T>::value();
-
-    T R[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) R[k] = T(0);
-    T a[RPT][M];
-
-    for (int64_t base = r0; base < r1; base += (int64_t)kWave * RPT) {
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const int64_t row = base + lane + (int64_t)kWave * i;
-            const bool ok = row < r1;
-#pragma unroll
-            for (int c = 0; c < M; ++c)
-                a[i][c] = (ok && c < m) ? Elem<Tin>::load(W + row + ld * c) : T(0);
-        }
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            if (j < m) {
-            const bool own = (lane == j);
-            T s = T(0);
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) s = fma(a[i][j], a[i][j], s);
-            const T rjj = own ? R[j] : T(0);
-            s = fma(rjj, rjj, s);
-            s = wave_sum(s);
-            const T u1 = read_lane(R[j], j);
-            T t = s + eps;
-            T alpha = dev_sqrt(t + eps);
-            alpha = (u1 > T(0)) ? -alpha : alpha;
-            t = fma(-alpha, u1, t);
-            const T beta = T(1) / dev_sqrt(t);
-            T v[RPT];
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) v[i] = beta * a[i][j];
-            const T vr = own ? beta * (u1 - alpha) : T(0);
-            if (own) R[j] = alpha;
-#pragma unroll
-            for (int kc = j + 1; kc < M; kc += CH) {
-                if (kc < m) {
-                T p[CH];
-#pragma unroll
-                for (int q = 0; q < CH; ++q) {
-                    const int k = kc + q;
-                    if (k < M) {
-                        T acc = vr * R[k];
-#pragma unroll
-                        for (int i = 0; i < RPT; ++i) acc = fma(v[i], a[i][k], acc);
-                        p[q] = acc;
-                    } else {
-                        p[q] = T(0);
-                    }
-                }
-                wave_allreduce_vec<CH>(p, lds);
-#pragma unroll
-                for (int q = 0; q < CH; ++q) {
-                    const int k = kc + q;
-                    if (k < M) {
-#pragma unroll
-                        for (int i = 0; i < RPT; ++i) a[i][k] = fma(-p[q], v[i], a[i][k]);
-                        R[k] = fma(-p[q], vr, R[k]);
-                    }
-                }
-                }
-            }
-            }
-        }
-    }
-    // Row `lane` of this slice's factor -> stacked output row slice*m + lane.
-    if (lane < m) {
-        const int64_t orow = slice * out_row0_stride + lane;
-        const bool keep = lane < kvalid;
-#pragma unroll
-        for (int c = 0; c < M; ++c)
-            if (c < m) out[orow + ld_out * c] = keep ? (double)R[c] : 0.0;
-    }
+    __shared__ __attribute__((aligned(16))) char smem[tsqr_rows_smem<M, RPT, Tin>()];
+    tsqr_rows_body<M, RPT, Tin>(W, rows, m, ld, rows_per_slice, nslices, out, ld_out,
+                                out_row0_stride, kvalid, blockIdx.x, smem);
 }
 
-// ----------------------------------------------------------------------------
-// Cooperative row-owner kernel, 8 < m <= M <= 64: NW waves share one row tile.
-//
-// Column k of the tile belongs to wave k mod NW (slot k / NW), so every wave
-// has trailing work at every step.  Lane l of each wave holds the rows
-// (tile_base + l + 64 i), i < RPT, of its columns and row l of the factor R
-// restricted to its columns.  Reflectors are published through LDS
-// (double-buffered, one barrier per column) with a look-ahead of one: while
-// the other waves apply reflector j to their trailing columns, the wave that
-// owns column j+1 first updates that column, builds reflector j+1 and
-// publishes it, and only then updates the rest of its columns.
-// ----------------------------------------------------------------------------
 template <int M, int NW, int RPT, typename Tin>
 __global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
     const Tin *__restrict__ W, int64_t rows, int m, int64_t ld,
     int64_t rows_per_slice, int64_t nslices, double *__restrict__ out,
     int64_t ld_out, int64_t out_row0_stride, int kvalid) {
-    using T = typename Elem<Tin>::acc;
-    constexpr int MW = M / NW;
-    static_assert(MW * NW == M, "M must be a multiple of NW");
-    __shared__ T vbuf[2][RPT][kWave];
-    __shared__ T vrbuf[2];
-    __shared__ T red[NW][kWave];
-
-    const int lane = lane_id();
-    const int w = threadIdx.x / kWave;
-    const int64_t slice = blockIdx.x;
-    const int64_t r0 = slice * rows_per_slice;
-    const int64_t r1 = min(rows, r0 + rows_per_slice);
-    T *lds = red[w];
-    const T eps = EpsFP<T>::value();
-
-    T R[MW];
-#pragma unroll
-    for (int k = 0; k < MW; ++k) R[k] = T(0);
-    T a[RPT][MW];
-
-    // Householder reflector of column jn, held by this wave in slot S
-    // (Algorithm 6): u = (R_jn,jn ; tile column), alpha = -sign(u_1) ||u||,
-    // v = (u - alpha e_1) / sqrt(t) with ||v||^2 = 2, published to LDS.
-    auto reflector = [&](auto slot_c, int jn) {
-        constexpr int S = decltype(slot_c)::value;
-        const bool own = (lane == jn);
-        T s = T(0);
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) s = fma(a[i][S], a[i][S], s);
-        const T rjj = own ? R[S] : T(0);
-        s = fma(rjj, rjj, s);
-        s = wave_sum(s);
-        const T u1 = read_lane(R[S], jn);
-        T t = s + eps;
-        const T t2 = t + eps;
-        T alpha = t2 * rsqrt_nr(t2);
-        alpha = (u1 > T(0)) ? -alpha : alpha;
-        t = fma(-alpha, u1, t);
-        const T beta = rsqrt_nr(t);
-        const int buf = jn & 1;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) vbuf[buf][i][lane] = beta * a[i][S];
-        if (own) {
-            vrbuf[buf] = beta * (u1 - alpha);
-            R[S] = alpha;
-        }
-    };
-
-    for (int64_t base = r0; base < r1; base += (int64_t)kWave * RPT) {
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const int64_t row = base + lane + (int64_t)kWave * i;
-            const bool ok = row < r1;
-#pragma unroll
-            for (int kk = 0; kk < MW; ++kk) {
-                const int c = NW * kk + w;
-                a[i][kk] = (ok && c < m) ? Elem<Tin>::load(W + row + ld * c) : T(0);
-            }
-        }
-        if (w == 0) reflector(std::integral_constant<int, 0>{}, 0);
-        static_for<0, MW>([&](auto jjc) {
-            constexpr int jj = decltype(jjc)::value;
-            constexpr int NT = MW - jj;  // slots jj..MW-1 may trail column j
-            for (int o = 0; o < NW; ++o) {
-                const int j = NW * jj + o;
-                if (j >= m) break;
-                const int buf = j & 1;
-                __syncthreads();  // reflector j is in vbuf[buf]
-                T v[RPT];
-#pragma unroll
-                for (int i = 0; i < RPT; ++i) v[i] = vbuf[buf][i][lane];
-                const T vr = (lane == j) ? vrbuf[buf] : T(0);
-                const bool first = (w > o);  // slot jj trails column j only in later waves
-                T p[NT];
-#pragma unroll
-                for (int q = 0; q < NT; ++q) {
-                    T acc = vr * R[jj + q];
-#pragma unroll
-                    for (int i = 0; i < RPT; ++i) acc = fma(v[i], a[i][jj + q], acc);
-                    p[q] = (q == 0 && !first) ? T(0) : acc;
-                }
-                wave_allreduce_vec<NT>(p, lds);
-                auto update = [&](int q) {
-#pragma unroll
-                    for (int qq = 0; qq < NT; ++qq) {
-                        if (qq == q) {
-#pragma unroll
-                            for (int i = 0; i < RPT; ++i) a[i][jj + qq] = fma(-p[qq], v[i], a[i][jj + qq]);
-                            R[jj + qq] = fma(-p[qq], vr, R[jj + qq]);
-                        }
-                    }
-                };
-                // look-ahead: column j+1 is slot jj of wave o+1, or slot jj+1 of wave 0
-                int qn = -1;
-                if (j + 1 < m) {
-                    if (o + 1 < NW) {
-                        if (w == o + 1) {
-                            qn = 0;
-                            update(0);
-                            reflector(std::integral_constant<int, jj>{}, j + 1);
-                        }
-                    } else if constexpr (jj + 1 < MW) {
-                        if (w == 0) {
-                            qn = 1;
-                            update(1);
-                            reflector(std::integral_constant<int, jj + 1>{}, j + 1);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < NT; ++q)
-                    if ((q > 0 || first) && q != qn) update(q);
-            }
-        });
-        // the first reflector of the next tile reuses buffer 0
-        __syncthreads();
-    }
-    if (lane < m) {
-        const int64_t orow = slice * out_row0_stride + lane;
-        const bool keep = lane < kvalid;
-#pragma unroll
-        for (int kk = 0; kk < MW; ++kk) {
-            const int c = NW * kk + w;
-            if (c < m) out[orow + ld_out * c] = keep ? (double)R[kk] : 0.0;
-        }
-    }
+    __shared__ __attribute__((aligned(16))) char smem[tsqr_coop_smem<M, NW, RPT, Tin>()];
+    (void)nslices;
+    tsqr_coop_body<M, NW, RPT, Tin>(W, rows, m, ld, rows_per_slice, blockIdx.x, out, ld_out,
+                                    out_row0_stride, kvalid, smem);
 }
 
 // ----------------------------------------------------------------------------
-// Column-owner workgroup kernel, 64 < m <= 256 * CPT.
+// Column-owner workgroup kernel, 128 < m <= 256 * CPT.
 //
 // Thread t owns the columns t + 256 c (c < CPT) of the current NB-row tile
 // (registers) and of the workgroup's triangular factor (row-major in global
@@ -409,6 +178,7 @@ struct CoopCfg {
 constexpr CoopCfg kCoop16[3] = {{4, 16}, {8, 16}, {16, 16}};
 constexpr CoopCfg kCoop32[3] = {{4, 8}, {8, 16}, {16, 8}};
 constexpr CoopCfg kCoop64[3] = {{8, 8}, {4, 4}, {16, 4}};
+constexpr CoopCfg kCoop128[3] = {{8, 2}, {4, 2}, {16, 2}};
 
 int coop_variant() {
     static int v = [] {
@@ -421,7 +191,7 @@ int coop_variant() {
 
 CoopCfg coop_cfg(int M) {
     const int v = coop_variant();
-    return M == 16 ? kCoop16[v] : M == 32 ? kCoop32[v] : kCoop64[v];
+    return M == 16 ? kCoop16[v] : M == 32 ? kCoop32[v] : M == 64 ? kCoop64[v] : kCoop128[v];
 }
 
 Shape shape_for(int64_t m) {
@@ -431,7 +201,7 @@ Shape shape_for(int64_t m) {
         sh.M = (int)cpow2((int)m);
         sh.rpt = 8;
         sh.tile = (int64_t)kWave * sh.rpt;
-    } else if (m <= 64) {
+    } else if (m <= 128) {
         sh.kind = Kind::Coop;
         sh.M = (int)cpow2((int)m);
         const CoopCfg c = coop_cfg(sh.M);
@@ -445,36 +215,20 @@ Shape shape_for(int64_t m) {
     return sh;
 }
 
-struct Level {
-    int64_t rows;            // rows of this level's input
-    int64_t nslices;
-    int64_t rows_per_slice;
-};
+using Level = TsqrLevel;
 
 std::vector<Level> plan(int64_t rows, int64_t m) {
     const Shape sh = shape_for(m);
-    std::vector<Level> lv;
-    int64_t r = rows;
-    for (;;) {
-        int64_t maxs, min_rows;
-        if (sh.kind == Kind::Rows) {
-            maxs = kMaxWaveSlices;
-            min_rows = std::max<int64_t>(4 * sh.tile, 4 * m);
-        } else if (sh.kind == Kind::Coop) {
-            maxs = kMaxCoopSlices;
-            min_rows = std::max<int64_t>(4 * sh.tile, 4 * m);
-        } else {
-            maxs = kMaxColsSlices;
-            min_rows = std::max<int64_t>(16 * sh.tile, 4 * m);
-        }
-        int64_t ns = std::min<int64_t>(maxs, std::max<int64_t>(1, ceil_div(r, min_rows)));
-        int64_t rps = ceil_div(ceil_div(r, ns), sh.tile) * sh.tile;
-        ns = ceil_div(r, rps);
-        lv.push_back({r, ns, rps});
-        if (ns == 1) break;
-        r = ns * m;
-    }
-    return lv;
+    TsqrPlanParams pp;
+    if (sh.kind == Kind::Rows)
+        pp = {kMaxWaveSlices, 4};
+    else if (sh.kind == Kind::Coop)
+        pp = {kMaxCoopSlices, 4};
+    else
+        pp = {kMaxColsSlices, 16};
+    TsqrLevel lv[kTsqrMaxLevels];
+    const int n = tsqr_plan_levels(rows, m, sh.tile, pp, lv);
+    return std::vector<Level>(lv, lv + n);
 }
 
 size_t level_out_doubles(const Level &l, int64_t m) { return (size_t)(l.nslices * m) * (size_t)m; }
@@ -548,6 +302,7 @@ int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Le
             TTSVD_COOP_CASE(16, kCoop16)
             TTSVD_COOP_CASE(32, kCoop32)
             TTSVD_COOP_CASE(64, kCoop64)
+            TTSVD_COOP_CASE(128, kCoop128)
             default:
                 return set_error(TTSVD_EUNSUPPORTED, "tsqr: bad column bucket %d", sh.M);
         }
@@ -584,7 +339,7 @@ size_t tsqr_workspace_bytes(int dtype, int64_t rows, int64_t m) {
     std::vector<Level> lv = plan(rows, m);
     size_t buf = 0, rws = 0;
     for (size_t i = 0; i + 1 < lv.size(); ++i) buf = std::max(buf, level_out_doubles(lv[i], m));
-    if (m > 64)
+    if (m > 128)
         for (const Level &l : lv) rws = std::max(rws, (size_t)(l.nslices * m) * (size_t)m);
     return (2 * buf + rws) * sizeof(double) + 256;
 }

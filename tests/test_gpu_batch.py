@@ -1,0 +1,191 @@
+"""GPU parity of the batched persistent launch (``ttsvd_decompose_batch``)
+against the CPU FP64 oracle, tensor by tensor, through the C ABI.
+
+Tolerances as in test_gpu_parity (FP64): identical ranks, kept singular values
+to 1e-10 relative, all of them to 1e-10 sigma_1, relative reconstruction
+errors equal to 1e-12.  FP32 storage: the bound c = (d - 1) 2^-24 + 1e-5 of
+test_gpu_precision against the oracle on the stored values.  Results must not
+depend on the number of workgroups (each work unit's arithmetic is fixed by
+the tree plan, not by which workgroup runs it), so those runs are compared
+bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import ttcheck
+from paper_2102_00104_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU host
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2102_00104_amd as tt  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype=torch.float64):
+    return ttcheck.dev_from_fortran(a, dtype, DEV)
+
+
+def mixed_batch():
+    """(dims, r_max, tol, X) cases: ragged shapes, d = 1 and 2, wide late
+    steps, steps of 64 and 128 columns, tolerances with clear margins."""
+    cases = []
+    for i, (dims, r_max) in enumerate([
+            ([2] * 10, 5), ([3, 4, 5, 6], 4), ([8, 8, 8], 16), ([4, 8, 8, 2], 16),
+            ([4, 4, 4, 4, 8, 4, 4], 16), ([5], 3), ([40, 30], 6), ([2] * 14, 32),
+            ([7, 3, 2, 5], 100), ([16, 4, 4], 8)]):
+        cases.append((dims, r_max, 0.0, synth.uniform(dims, seed=100 + i)))
+    cases.append(([3, 4, 5, 2, 3], 50, 1e-12, synth.exact_tt([3, 4, 5, 2, 3], 2, seed=41)))
+    X = synth.exact_tt([4] * 6, 3, seed=42, noise=1e-3, noise_seed=43)
+    cases.append(([4] * 6, 16, 1e-2, X))
+    X = synth.exact_tt([2] * 12, 4, seed=44, noise=1e-9, noise_seed=45)
+    cases.append(([2] * 12, 16, 1e-6, X))
+    return cases
+
+
+def run_batch(cases, dtype=torch.float64, cfg=None, fetch=True):
+    Xs = [dev(X, dtype) for (_, _, _, X) in cases]
+    return tt.ttsvd_decompose_batch(Xs, [c[0] for c in cases], [c[1] for c in cases],
+                                    [c[2] for c in cases], cfg=cfg, fetch=fetch), Xs
+
+
+def test_batch_matches_oracle_per_tensor():
+    cases = mixed_batch()
+    log("batch of %d tensors" % len(cases))
+    res, _ = run_batch(cases)
+    for (dims, r_max, tol, X), g in zip(cases, res):
+        log("  %s r_max=%d tol=%g ranks=%s" % (dims, r_max, tol, g.ranks))
+        o = oracle.ttsvd(X, dims, r_max, tol)
+        if tol > 0:
+            assert min(o.margins[1:] or [1.0]) > 1e-3
+        if len(dims) == 1:
+            assert g.ranks == [1, 1]
+            assert np.array_equal(g.cores[0].cpu().numpy(), X)
+            continue
+        cores, Xg = ttcheck.compare_tt(g, o, X, tt.core_array)
+        err2 = float(np.sum((X - Xg) ** 2))
+        assert abs(err2 - g.err_bound ** 2) <= 1e-10 * float(np.sum(X * X))
+        assert abs(g.norm_sigma - np.linalg.norm(X)) <= 1e-12 * np.linalg.norm(X)
+
+
+def test_batch_equals_single_path_ranks_and_sigma():
+    cases = mixed_batch()[:8]
+    res, Xs = run_batch(cases)
+    for (dims, r_max, tol, _), g, X in zip(cases, res, Xs):
+        s = tt.ttsvd_decompose(X, dims, r_max, tol)
+        assert s.ranks == g.ranks
+        for j in range(1, len(dims)):
+            a, b = np.asarray(g.sigma[j]), np.asarray(s.sigma[j])
+            assert np.max(np.abs(a - b)) <= 1e-12 * b[0]
+
+
+def test_batch_independent_of_grid_size_and_deterministic():
+    cases = mixed_batch()
+    full, _ = run_batch(cases)
+    again, _ = run_batch(cases)
+    cfg = tt.batch_default_config()
+    cfg.grid = 1                       # one workgroup runs every unit
+    one, _ = run_batch(cases, cfg=cfg)
+    cfg.grid = 7
+    seven, _ = run_batch(cases, cfg=cfg)
+    for a, b, c, e in zip(full, again, one, seven):
+        assert a.ranks == b.ranks == c.ranks == e.ranks
+        for j in range(len(a.dims)):
+            ca = a.cores[j].cpu().numpy()
+            for other in (b, c, e):
+                assert np.array_equal(ca, other.cores[j].cpu().numpy())
+            if j:
+                assert a.sigma[j] == b.sigma[j] == c.sigma[j] == e.sigma[j]
+
+
+@pytest.mark.parametrize("min_tiles,max_slices", [(1, 1), (2, 3), (8, 1024)])
+def test_batch_tree_shapes_match_oracle(min_tiles, max_slices):
+    # different reduction trees (one slice per level, ragged slices, many slices)
+    cases = [([2] * 16, 8, 0.0, synth.uniform([2] * 16, seed=61)),
+             ([4, 4, 4, 4, 8, 4, 4], 16, 0.0, synth.uniform([4, 4, 4, 4, 8, 4, 4], seed=62))]
+    cfg = tt.batch_default_config()
+    cfg.min_tiles, cfg.max_slices = min_tiles, max_slices
+    res, _ = run_batch(cases, cfg=cfg)
+    for (dims, r_max, tol, X), g in zip(cases, res):
+        ttcheck.compare_tt(g, oracle.ttsvd(X, dims, r_max, tol), X, tt.core_array)
+
+
+def test_batch_zero_and_rank_one_tensors():
+    rng = np.random.default_rng(53)
+    a, b, c = rng.standard_normal(5), rng.standard_normal(6), rng.standard_normal(7)
+    R1 = np.multiply.outer(np.multiply.outer(a, b), c).reshape(-1, order="F")
+    Xs = [torch.zeros(48, dtype=torch.float64, device=DEV), dev(R1)]
+    res = tt.ttsvd_decompose_batch(Xs, [[2, 3, 8], [5, 6, 7]], [5, 10], [1e-6, 1e-10])
+    assert res[0].ranks == [1, 1, 1, 1]
+    assert all(torch.isfinite(c).all() for c in res[0].cores)
+    assert res[1].ranks == [1, 1, 1, 1]
+
+
+def test_batch_fp32_storage_within_precision_bound():
+    specs = [([2] * 14, 7), ([4, 4, 4, 4, 4, 4], 5), ([8, 2, 4, 2, 8], 6), ([2, 4, 8, 4, 2, 2], 3)]
+    cases = []
+    for i, (dims, rank) in enumerate(specs):
+        X = synth.exact_tt(dims, rank, seed=70 + i, noise=1e-6, noise_seed=80 + i,
+                           unit_variance=True, relative_noise=True)
+        cases.append((dims, 16, 1e-5, X))
+    res, Xs = run_batch(cases, dtype=torch.float32)
+    u = 2.0 ** -24
+    for (dims, r_max, tol, X), g, Xd in zip(cases, res, Xs):
+        Xs64 = Xd.to(torch.float64).cpu().numpy()
+        o = oracle.ttsvd(Xs64, dims, r_max, tol)
+        assert min(o.margins[1:]) > 1e-2
+        assert g.ranks == o.ranks
+        c = (len(dims) - 1) * u + 1e-5
+        for j in range(1, len(dims)):
+            r = o.ranks[j]
+            assert np.max(np.abs(np.asarray(g.sigma[j])[:r] - o.sigma[j][:r])) <= c * o.sigma[j][0]
+        e = oracle.rel_error(Xs64, oracle.tt_full(ttcheck.host_cores(g, tt.core_array)))
+        eo = oracle.rel_error(Xs64, oracle.tt_full(o.cores))
+        assert abs(e - eo) <= c
+
+
+def test_batch_autotune_and_cached_config():
+    cases = mixed_batch()[:6]
+    Xs = [dev(X) for (_, _, _, X) in cases]
+    dims = [c[0] for c in cases]
+    rm = [c[1] for c in cases]
+    tl = [c[2] for c in cases]
+    best, ms = tt.ttsvd_batch_autotune(Xs, dims, rm, tl)
+    assert ms > 0 and best.min_tiles >= 1 and best.max_slices >= 1
+    a = tt.ttsvd_decompose_batch(Xs, dims, rm, tl)             # cached configuration
+    b = tt.ttsvd_decompose_batch(Xs, dims, rm, tl, cfg=best)
+    for x, y in zip(a, b):
+        assert x.ranks == y.ranks
+        for j in range(len(x.dims)):
+            assert np.array_equal(x.cores[j].cpu().numpy(), y.cores[j].cpu().numpy())
+
+
+def test_batch_errors():
+    X = torch.zeros(64, dtype=torch.float64, device=DEV)
+    Y = torch.zeros(64, dtype=torch.float32, device=DEV)
+    with pytest.raises(tt.TTSVDError) as e:
+        tt.ttsvd_decompose_batch([X, Y], [[4, 16], [4, 16]], 3, 0.0)
+    assert e.value.code == -5                                  # mixed dtypes
+    big = torch.zeros(16 ** 3, dtype=torch.float64, device=DEV)
+    with pytest.raises(tt.TTSVDError) as e:
+        tt.ttsvd_decompose_batch([big], [[16, 16, 16]], 40, 0.0)
+    assert e.value.code == -5                                  # 256 columns
+    with pytest.raises(tt.TTSVDError) as e:
+        tt.ttsvd_decompose_batch([X], [[4, 16]], 0, 0.0)
+    assert e.value.code == -1
+    bad = torch.tensor([1.0, float("nan")] * 8, dtype=torch.float64, device=DEV)
+    with pytest.raises(tt.TTSVDError) as e:
+        tt.ttsvd_decompose_batch([X, bad], [[4, 16], [2, 2, 4]], 3, 0.0)
+    assert e.value.code == -4

@@ -18,6 +18,7 @@ import numpy as np
 import pytest
 
 import oracle
+import ttcheck
 from paper_2102_00104_amd import synth
 
 torch = pytest.importorskip("torch")
@@ -37,8 +38,7 @@ def log(msg):
 
 
 def dev_from_fortran(a, dtype=torch.float64):
-    flat = np.asfortranarray(a).reshape(-1, order="F")
-    return torch.from_numpy(np.ascontiguousarray(flat)).to(DEV, dtype=dtype)
+    return ttcheck.dev_from_fortran(a, dtype, DEV)
 
 
 def sign_rows(R):
@@ -140,28 +140,7 @@ def test_gemm_reshape_bit_exact(rows, cols, k, n_next, pad):
 
 
 def _compare_tt(g, o, X, kept_rel=1e-10, err_abs=1e-12, recon=None):
-    assert g.ranks == o.ranks, (g.ranks, o.ranks)
-    d = len(o.dims)
-    for j in range(1, d):
-        sg = np.asarray(g.sigma[j])
-        so = o.sigma[j]
-        assert len(sg) == len(so)
-        r = o.ranks[j]
-        assert np.all(np.abs(sg[:r] - so[:r]) <= kept_rel * so[:r]), j
-        assert np.max(np.abs(sg - so)) <= kept_rel * so[0], j
-    cores = [tt.core_array(c, (g.ranks[j], g.dims[j], g.ranks[j + 1]))
-             for j, c in enumerate(g.cores)]
-    Xg = oracle.tt_full(cores)
-    Xo = oracle.tt_full(o.cores)
-    eg, eo = oracle.rel_error(X, Xg), oracle.rel_error(X, Xo)
-    assert abs(eg - eo) <= err_abs, (eg, eo)
-    if recon is not None:
-        assert np.linalg.norm(Xg - Xo) <= recon * np.linalg.norm(X)
-    for j in range(1, d):
-        r, n, rn = cores[j].shape
-        M = cores[j].reshape(r, n * rn, order="F")
-        assert np.max(np.abs(M @ M.T - np.eye(r))) <= 1e-12
-    return cores, Xg
+    return ttcheck.compare_tt(g, o, X, tt.core_array, kept_rel, err_abs, recon)
 
 
 def test_small_exact_tt_workload():
