@@ -128,6 +128,204 @@ def precision_forms(tt, X64, dims, r_max, steps, warmup, f64_sec, f64_res):
     return out
 
 
+def batched(tt, steps, warmup, count=512, parity_elems=1 << 24):
+    """Many-tensor form: 512 FP32 exact-TT tensors of mixed shapes (d ~
+    U{6..20}, n_i in {2, 4, 8}, 4 KiB .. 64 MiB, bond ranks U{2..16}, unit-
+    variance cores, 1e-6 relative noise), r_max = 16, tol = 1e-5, decomposed
+    in one persistent launch after autotuning; aggregate effective GB/s, a
+    per-tensor parity check against the FP64 oracle on a bounded sample, and
+    the same tensors decomposed one by one with the single-tensor path."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2102_00104_amd import model, synth
+    dev = torch.device("cuda:0")
+    specs = synth.batch_specs(count=count, seed=3)
+    dims_list = [d for d, _ in specs]
+    Xs = [synth.exact_tt_device(d, r, seed=10000 + i, noise=1e-6, noise_seed=20000 + i,
+                                device=dev, dtype=torch.float32)
+          for i, (d, r) in enumerate(specs)]
+    torch.cuda.synchronize()
+    in_bytes = sum(4 * synth.prod(d) for d in dims_list)
+    log("batched: %d tensors, %.1f MiB FP32; autotuning" % (len(Xs), in_bytes / 2 ** 20))
+    cfg, tune_ms = tt.ttsvd_batch_autotune(Xs, dims_list, 16, 1e-5)
+    log("batched: best %s (%.3f ms)" % (cfg.as_dict(), tune_ms))
+    st = torch.cuda.current_stream().cuda_stream
+    n, xs, d, dims, rm, tl = tt._batch_args(Xs, dims_list, 16, 1e-5, st)
+    outs = (tt.TTStruct * n)()
+    L = tt.lib()
+
+    def once():
+        rc = L.ttsvd_decompose_batch(n, xs, d, dims, rm, tl, ctypes.byref(cfg), st, outs)
+        if rc != 0:
+            raise tt.TTSVDError(rc, L.ttsvd_last_error().decode())
+
+    def free():
+        for t in range(n):
+            L.ttsvd_tt_free(ctypes.byref(outs[t]))
+
+    for _ in range(warmup):
+        once()
+        free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        once()
+        if k + 1 < steps:
+            free()
+    sec = (time.perf_counter() - t0) / steps
+    ranks = [[int(outs[t].ranks[i]) for i in range(d[t] + 1)] for t in range(n)]
+    free()
+    # time per phase kind, from the kernel's device clock
+    tt.ttsvd_profile_reset()
+    tt.ttsvd_profile_enable(True)
+    try:
+        once()
+        free()
+        phases = {s_["name"]: round(s_["total_ms"], 3) for s_ in tt.ttsvd_profile_read()}
+    finally:
+        tt.ttsvd_profile_enable(False)
+        tt.ttsvd_profile_reset()
+    log("batched: phases %s" % phases)
+    abytes = sum(model.algorithmic_bytes(dl, rk, 4) for dl, rk in zip(dims_list, ranks))
+    log("batched: %.3f ms per batch, %.1f GB/s" % (sec * 1e3, abytes / sec / 1e9))
+
+    # parity on a bounded sample: smallest tensors first, up to parity_elems elements
+    res = tt.ttsvd_decompose_batch(Xs, dims_list, 16, 1e-5, cfg=cfg)
+    order = sorted(range(n), key=lambda t: synth.prod(dims_list[t]))
+    checked = passed = 0
+    budget = parity_elems
+    u = 2.0 ** -24
+    t_or = time.perf_counter()
+    for t in order:
+        size = synth.prod(dims_list[t])
+        if size > budget:
+            break
+        budget -= size
+        Xh = Xs[t].to(torch.float64).cpu().numpy()
+        o = oracle.ttsvd(Xh, dims_list[t], 16, 1e-5)
+        g = res[t]
+        c = (len(dims_list[t]) - 1) * u + 1e-5
+        ok = g.ranks == o.ranks
+        if ok:
+            for j in range(1, len(dims_list[t])):
+                r = o.ranks[j]
+                ok &= bool(np.max(np.abs(np.asarray(g.sigma[j])[:r] - o.sigma[j][:r]))
+                           <= c * o.sigma[j][0])
+            cores = [tt.core_array(cc, (g.ranks[j], g.dims[j], g.ranks[j + 1]))
+                     for j, cc in enumerate(g.cores)]
+            e = oracle.rel_error(Xh, oracle.tt_full(cores))
+            ok &= abs(e - oracle.rel_error(Xh, oracle.tt_full(o.cores))) <= c
+        checked += 1
+        passed += int(ok)
+    t_or = time.perf_counter() - t_or
+    log("batched: parity %d / %d tensors (%.1f s of oracle)" % (passed, checked, t_or))
+
+    # the same tensors one by one through the single-tensor path
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for X, dl in zip(Xs, dims_list):
+        tt.ttsvd_decompose(X, dl, 16, 1e-5)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    log("batched: one by one %.1f ms" % (seq * 1e3))
+    return {"value": round(abytes / sec / 1e9, 2), "unit": "GB/s", "ms_per_batch": round(sec * 1e3, 3),
+            "tensors": n, "input_bytes": in_bytes, "algorithmic_bytes": abytes,
+            "hbm_roofline_frac": round(abytes / sec / 1e9 / HBM_PEAK_GBS, 4),
+            "config": cfg.as_dict(), "autotune_best_ms": round(tune_ms, 3), "phases_ms": phases,
+            "parity": {"checked": checked, "passed": passed,
+                       "sample": "smallest tensors up to %d elements in total" % parity_elems},
+            "one_by_one_ms": round(seq * 1e3, 3), "speedup_vs_one_by_one": round(seq / sec, 2)}
+
+
+def serve_trace(tt, trace, workers, max_batch, live_cap=48 << 30):
+    """Replay a request trace in real time against a Server: each request's
+    FP32 tensor is synthesised on the device at its arrival time (on a side
+    stream), then submitted.  Returns per-request records."""
+    import torch
+
+    from paper_2102_00104_amd import synth
+    dev = torch.device("cuda:0")
+    cfg = tt.server_default_config()
+    cfg.workers, cfg.max_batch = workers, max_batch
+    syn = torch.cuda.Stream()
+    live = {}          # ticket -> (tensor, bytes, request index)
+    live_bytes = 0
+    rec = {}
+
+    def collect(srv, wait_ms):
+        nonlocal live_bytes
+        for c in srv.poll(max_n=512, wait_ms=wait_ms):
+            X, b, i = live.pop(c["ticket"])
+            live_bytes -= b
+            r = c["result"]
+            rec[i].update(status=c["status"], t_submit=c["t_submit"], t_start=c["t_start"],
+                          t_done=c["t_done"], batch=c["batch_size"], batched=c["batched"],
+                          ranks=r.ranks if r is not None else None)
+            del X
+
+    with tt.Server(cfg) as srv:
+        t0 = tt.server_clock()
+        for i, q in enumerate(trace):
+            while True:  # wait for the arrival time (and for memory), collecting results
+                left = t0 + q["t"] - tt.server_clock()
+                if left <= 0 and live_bytes < live_cap:
+                    break
+                collect(srv, max(1, int(left * 1e3)) if left > 0 else 1)
+            with torch.cuda.stream(syn):
+                X = synth.exact_tt_device(q["dims"], q["ranks"], seed=40000 + i, noise=1e-6,
+                                          noise_seed=50000 + i, device=dev, dtype=torch.float32)
+            syn.synchronize()
+            rec[i] = dict(arrival=t0 + q["t"], ready=tt.server_clock())
+            ticket = srv.submit(X, q["dims"], q["r_max"], q["tol"])
+            b = X.numel() * 4
+            live[ticket] = (X, b, i)
+            live_bytes += b
+        while srv.pending() > 0 or live:
+            collect(srv, 50)
+    return [rec[i] for i in range(len(trace))]
+
+
+def serving(tt, duration):
+    """Serving workload: Poisson arrivals at 200/s over `duration` seconds,
+    sizes 1 MiB .. 4 GiB (FP32), r_max U{4..64}, tol log-uniform in
+    [1e-5, 1e-2]; the batching server (4 workers) against one worker that
+    runs every request alone (the sequential plain path), same trace."""
+    import numpy as np
+
+    from paper_2102_00104_amd import model, synth
+    trace = synth.serving_trace(duration_s=duration, rate=200.0, seed=4)
+
+    def summary(recs):
+        ok = [r for r in recs if r.get("status") == 0]
+        lat = np.array([r["t_done"] - r["ready"] for r in ok])
+        lat_arr = np.array([r["t_done"] - r["arrival"] for r in ok])
+        span = max(r["t_done"] for r in ok) - min(r["ready"] for r in ok)
+        abytes = sum(model.algorithmic_bytes(q["dims"], r["ranks"], 4)
+                     for q, r in zip(trace, recs) if r.get("status") == 0)
+        return {"completed": len(ok), "failed": len(recs) - len(ok),
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                "p50_ms_from_arrival": round(float(np.percentile(lat_arr, 50)) * 1e3, 3),
+                "p99_ms_from_arrival": round(float(np.percentile(lat_arr, 99)) * 1e3, 3),
+                "aggregate_GBs": round(abytes / span / 1e9, 2), "span_s": round(span, 3),
+                "batched_requests": sum(1 for r in ok if r["batched"]),
+                "max_batch_seen": max(r["batch"] for r in ok)}
+
+    log("serving: %d requests over %.1f s (%.1f GiB FP32)" % (
+        len(trace), duration, sum(synth.prod(q["dims"]) for q in trace) * 4 / 2 ** 30))
+    fast = summary(serve_trace(tt, trace, workers=4, max_batch=512))
+    log("serving: batching server %s" % fast)
+    seq = summary(serve_trace(tt, trace, workers=1, max_batch=1))
+    log("serving: sequential %s" % seq)
+    return {"requests": len(trace), "duration_s": duration, "rate_per_s": 200.0,
+            "latency": "request tensor resident on the device -> cores ready",
+            "server": fast, "sequential": seq}
+
+
 def cpu_baseline(d_sample, r_max):
     """The CPU FP64 oracle on a bounded sample of the same workload."""
     import numpy as np
@@ -157,6 +355,9 @@ def main():
     ap.add_argument("--cpu-sample-d", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (row slabs of the "
@@ -224,6 +425,10 @@ def main():
     if not args.no_precision:
         line["precision_forms"] = precision_forms(tt, X, head["dims"], args.r_max, args.steps,
                                                   args.warmup, head["sec"], head["res"])
+    if not args.no_batched:
+        line["batched"] = batched(tt, args.steps, args.warmup)
+    if not args.no_serving:
+        line["serving"] = serving(tt, args.serve_seconds)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a 2^%d sample" % args.cpu_sample_d)
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_d, args.r_max)

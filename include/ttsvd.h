@@ -210,6 +210,52 @@ int ttsvd_batch_autotune(int count, const ttsvd_tensor *X, const int *d,
                          const double *tol, hipStream_t stream,
                          ttsvd_batch_config *best, double *best_ms);
 
+/*
+ * Serving runtime: requests that arrive over time are queued in FIFO order,
+ * admitted while the sum of their device footprints (ttsvd_footprint_bytes)
+ * stays within a budget, and run by worker threads, each on its own stream.
+ * Small requests (every step at most 128 columns, at most batch_max_elems
+ * elements, dense) waiting together are decomposed in one batched launch;
+ * the others run alone.  Timestamps are seconds of ttsvd_server_clock().
+ */
+typedef struct ttsvd_server ttsvd_server;
+
+typedef struct ttsvd_server_config {
+    size_t hbm_budget;        /* bytes of workspace + outputs admitted at once (> 0)  */
+    int workers;              /* worker threads / streams, 1..64                      */
+    int max_batch;            /* requests per batched launch (1: never batch)         */
+    int64_t batch_max_elems;  /* largest tensor eligible for a batched launch         */
+} ttsvd_server_config;
+
+typedef struct ttsvd_completion {
+    uint64_t ticket;          /* from ttsvd_server_submit                            */
+    int status;               /* TTSVD_OK or the error of the decomposition          */
+    int batch_size;           /* requests in the launch that ran it                  */
+    int batched;              /* 1: ran in a batched launch, 0: ttsvd_decompose      */
+    double t_submit, t_start, t_done;
+    ttsvd_tt tt;              /* result (status TTSVD_OK); release with ttsvd_tt_free */
+} ttsvd_completion;
+
+/* Defaults: 64 GiB budget, 4 workers, batches of up to 512, 2^24 elements. */
+int ttsvd_server_default_config(ttsvd_server_config *cfg);
+/* Start a server on the calling thread's current device.  Errors: TTSVD_EINVAL. */
+int ttsvd_server_create(const ttsvd_server_config *cfg, ttsvd_server **out);
+/* Queue a decomposition of X (device memory that must stay valid and unchanged
+ * until its completion is returned; X->stream is ignored).  Arguments as in
+ * ttsvd_decompose; *ticket identifies the request.  Errors: TTSVD_EINVAL,
+ * TTSVD_EUNSUPPORTED. */
+int ttsvd_server_submit(ttsvd_server *s, const ttsvd_tensor *X, const int64_t *dims, int d,
+                        int64_t r_max, double tol, uint64_t *ticket);
+/* Move up to max finished requests into out (waiting up to wait_ms for the
+ * first one); *n receives the count. */
+int ttsvd_server_poll(ttsvd_server *s, ttsvd_completion *out, int max, int wait_ms, int *n);
+/* Requests submitted and not yet finished. */
+int64_t ttsvd_server_pending(ttsvd_server *s);
+/* Finish every queued request, stop the workers and free unpolled results. */
+void ttsvd_server_destroy(ttsvd_server *s);
+/* The steady clock of the completion timestamps, in seconds. */
+double ttsvd_server_clock(void);
+
 /* Release the buffers of a ttsvd_tt filled by ttsvd_decompose or
  * ttsvd_decompose_batch (NULL-safe). */
 void ttsvd_tt_free(ttsvd_tt *tt);

@@ -30,7 +30,10 @@ EXPORTED = ["ttsvd_tsqr_r", "ttsvd_tsqr_workspace_size", "ttsvd_gemm_reshape",
             "ttsvd_decompose", "ttsvd_tt_free", "ttsvd_footprint_bytes",
             "ttsvd_strerror", "ttsvd_last_error", "ttsvd_version",
             "ttsvd_profile_enable", "ttsvd_profile_reset", "ttsvd_profile_read",
-            "ttsvd_batch_default_config", "ttsvd_decompose_batch", "ttsvd_batch_autotune"]
+            "ttsvd_batch_default_config", "ttsvd_decompose_batch", "ttsvd_batch_autotune",
+            "ttsvd_server_default_config", "ttsvd_server_create", "ttsvd_server_submit",
+            "ttsvd_server_poll", "ttsvd_server_pending", "ttsvd_server_destroy",
+            "ttsvd_server_clock"]
 
 
 class TTSVDError(RuntimeError):
@@ -90,6 +93,30 @@ class BatchConfig(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class ServerConfig(ctypes.Structure):
+    """ctypes mirror of ``ttsvd_server_config``."""
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t),
+        ("workers", ctypes.c_int),
+        ("max_batch", ctypes.c_int),
+        ("batch_max_elems", ctypes.c_int64),
+    ]
+
+
+class Completion(ctypes.Structure):
+    """ctypes mirror of ``ttsvd_completion``."""
+    _fields_ = [
+        ("ticket", ctypes.c_uint64),
+        ("status", ctypes.c_int),
+        ("batch_size", ctypes.c_int),
+        ("batched", ctypes.c_int),
+        ("t_submit", ctypes.c_double),
+        ("t_start", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+        ("tt", TTStruct),
+    ]
+
+
 _lib = None
 _hip = None
 
@@ -141,6 +168,23 @@ def lib() -> ctypes.CDLL:
             ctypes.c_int, ctypes.POINTER(TensorStruct), ctypes.POINTER(ctypes.c_int),
             ctypes.POINTER(i64), ctypes.POINTER(i64), dp, vp, ctypes.POINTER(BatchConfig), dp]
         L.ttsvd_batch_autotune.restype = ctypes.c_int
+        L.ttsvd_server_default_config.argtypes = [ctypes.POINTER(ServerConfig)]
+        L.ttsvd_server_default_config.restype = ctypes.c_int
+        L.ttsvd_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+        L.ttsvd_server_create.restype = ctypes.c_int
+        L.ttsvd_server_submit.argtypes = [vp, ctypes.POINTER(TensorStruct), ctypes.POINTER(i64),
+                                          ctypes.c_int, i64, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_uint64)]
+        L.ttsvd_server_submit.restype = ctypes.c_int
+        L.ttsvd_server_poll.argtypes = [vp, ctypes.POINTER(Completion), ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]
+        L.ttsvd_server_poll.restype = ctypes.c_int
+        L.ttsvd_server_pending.argtypes = [vp]
+        L.ttsvd_server_pending.restype = i64
+        L.ttsvd_server_destroy.argtypes = [vp]
+        L.ttsvd_server_destroy.restype = None
+        L.ttsvd_server_clock.argtypes = []
+        L.ttsvd_server_clock.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -325,3 +369,69 @@ def core_array(t, shape):
     """A Fortran-ordered numpy copy of a flat device core."""
     import numpy as np
     return np.asarray(t.cpu().numpy()).reshape(shape, order="F")
+
+
+# ----------------------------------------------------------------- serving
+
+def server_default_config() -> ServerConfig:
+    c = ServerConfig()
+    _check(lib().ttsvd_server_default_config(ctypes.byref(c)))
+    return c
+
+
+def server_clock() -> float:
+    """The steady clock (seconds) of the server's timestamps."""
+    return float(lib().ttsvd_server_clock())
+
+
+class Server:
+    """``ttsvd_server_*``: queued TT-SVD requests on worker streams.  The
+    submitted tensors must stay alive until their completion is polled."""
+
+    def __init__(self, cfg: Optional[ServerConfig] = None):
+        self._h = ctypes.c_void_p()
+        cfg = cfg if cfg is not None else server_default_config()
+        _check(lib().ttsvd_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+
+    def submit(self, X, dims: Sequence[int], r_max: int, tol: float) -> int:
+        xs = TensorStruct(X.data_ptr(), dtype_code(X), 0, None)
+        arr = (ctypes.c_int64 * len(dims))(*[int(n) for n in dims])
+        t = ctypes.c_uint64(0)
+        _check(lib().ttsvd_server_submit(self._h, ctypes.byref(xs), arr, len(dims), int(r_max),
+                                         float(tol), ctypes.byref(t)))
+        return int(t.value)
+
+    def poll(self, max_n: int = 256, wait_ms: int = 0, fetch: bool = False, device=None) -> list:
+        """Finished requests: dicts with ticket, status, batch_size, the three
+        timestamps and the result (a TT; its cores only if fetch)."""
+        arr = (Completion * max_n)()
+        n = ctypes.c_int(0)
+        _check(lib().ttsvd_server_poll(self._h, arr, max_n, int(wait_ms), ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = arr[i]
+            item = dict(ticket=int(c.ticket), status=int(c.status), batch_size=int(c.batch_size),
+                        batched=bool(c.batched),
+                        t_submit=float(c.t_submit), t_start=float(c.t_start),
+                        t_done=float(c.t_done), result=None)
+            if c.status == TTSVD_OK:
+                try:
+                    item["result"] = _to_tt(c.tt, device, _stream(None), fetch)
+                finally:
+                    lib().ttsvd_tt_free(ctypes.byref(arr[i].tt))
+            out.append(item)
+        return out
+
+    def pending(self) -> int:
+        return int(lib().ttsvd_server_pending(self._h))
+
+    def close(self) -> None:
+        if self._h:
+            lib().ttsvd_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -125,6 +125,34 @@ int keep_pool_memory(hipStream_t s) {
     return TTSVD_OK;
 }
 
+hipError_t coop_launch(const void *fn, dim3 grid, dim3 block, void **args, size_t lds,
+                       hipStream_t s) {
+    static std::mutex mu;
+    static hipEvent_t last[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (last[dev]) {
+        e = hipStreamWaitEvent(s, last[dev], 0);
+        if (e != hipSuccess) return e;
+    }
+    e = hipLaunchCooperativeKernel(fn, grid, block, args, lds, s);
+    if (e != hipSuccess) return e;
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev, s);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return e;
+    }
+    if (last[dev]) (void)hipEventDestroy(last[dev]);
+    last[dev] = ev;
+    return hipSuccess;
+}
+
 }  // namespace ttsvd
 
 using namespace ttsvd;

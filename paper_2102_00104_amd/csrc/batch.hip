@@ -18,6 +18,10 @@
 // through, so small and large tensors share the machine.  Every loop has a
 // bound known before it starts and every workgroup reaches every barrier, so
 // the grid always drains.
+// Bodies in this translation unit read the thread index through an opaque
+// statement (see thread_id in common.h).
+#define TTSVD_PERSISTENT_KERNEL 1
+
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -104,6 +108,7 @@ struct BArgs {
     int ts;
     TsqrPlanParams pr, pc;  // planner parameters, row-owner / cooperative bodies
     GridBarrier *bar;
+    uint64_t *clk;  // optional: (time, phase) after every barrier, by workgroup 0
 };
 
 __host__ __device__ inline void make_bstep(BStep &s, int ts, TsqrPlanParams pr, TsqrPlanParams pc,
@@ -368,6 +373,14 @@ __global__ __launch_bounds__(kBThreads) void batch_kernel(BArgs a) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ int bar_flag;
     unsigned gen = 0;
+    // phase clock: 100 MHz wall clock after each barrier (workgroup 0 only)
+    auto stamp = [&](int phase) {
+        if (a.clk && blockIdx.x == 0 && threadIdx.x == 0) {
+            a.clk[2 * gen] = wall_clock64();
+            a.clk[2 * gen + 1] = (uint64_t)phase;
+        }
+    };
+    stamp(-1);
     uint32_t *pref = reinterpret_cast<uint32_t *>(smem + align256(kBBodySmem));
     uint32_t *tmp = pref + a.ntask + 1;
 
@@ -389,6 +402,7 @@ __global__ __launch_bounds__(kBThreads) void batch_kernel(BArgs a) {
                 __syncthreads();
             }
             if (!grid_barrier(a.bar, gen, &bar_flag)) return;
+            stamp(0);
         }
         // SVD, rank, core, next step's shape
         {
@@ -400,6 +414,7 @@ __global__ __launch_bounds__(kBThreads) void batch_kernel(BArgs a) {
                 __syncthreads();
             }
             if (!grid_barrier(a.bar, gen, &bar_flag)) return;
+            stamp(1);
         }
         // TSMM + reshape
         {
@@ -419,6 +434,7 @@ __global__ __launch_bounds__(kBThreads) void batch_kernel(BArgs a) {
                 __syncthreads();
             }
             if (!grid_barrier(a.bar, gen, &bar_flag)) return;
+            stamp(2);
         }
     }
 }
@@ -604,6 +620,9 @@ int run_batch(int count, const ttsvd_tensor *X, const int *d, const int64_t *dim
     const size_t o_sig = take(sizeof(double) * std::max<size_t>(bp.sigma, 1));
     const size_t o_one = take(sizeof(double));
     const size_t o_bar = take(sizeof(GridBarrier));
+    const bool clocks = prof_on();
+    const size_t nclk = (size_t)bp.nrounds * (kTsqrMaxLevels + 2) + 1;
+    const size_t o_clk = take(clocks ? nclk * 2 * sizeof(uint64_t) : 0);
     const size_t meta = off;  // the host image below covers [0, meta): state starts at zero
     std::vector<size_t> o_w0(n), o_w1(n), o_r(n), o_tq(n);
     for (int t = 0; t < n; ++t) {
@@ -691,6 +710,7 @@ int run_batch(int count, const ttsvd_tensor *X, const int *d, const int64_t *dim
         args.pr = pr;
         args.pc = pc;
         args.bar = (GridBarrier *)(ws + o_bar);
+        args.clk = clocks ? (uint64_t *)(ws + o_clk) : nullptr;
         const void *fn = kernel_ptr(bp.dtype, cfg.tile_set);
         const size_t lds = batch_smem_bytes(n);
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -717,7 +737,7 @@ int run_batch(int count, const ttsvd_tensor *X, const int *d, const int64_t *dim
                  bp.dtype == TTSVD_F64 ? "double" : bp.dtype == TTSVD_F32 ? "float" : "ttsvd::bf16",
                  cfg.tile_set);
         prof_begin(s, name, 0.0, 0.0);
-        const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBThreads), kargs, lds, s);
+        const hipError_t e = coop_launch(fn, dim3(grid), dim3(kBThreads), kargs, lds, s);
         prof_end(s);
         if (e != hipSuccess)
             return fail(set_error(TTSVD_EHIP, "batch: cooperative launch: %s", hipGetErrorString(e)));
@@ -726,7 +746,9 @@ int run_batch(int count, const ttsvd_tensor *X, const int *d, const int64_t *dim
     std::vector<StepState> hst(ns);
     std::vector<double> hsig(std::max<size_t>(bp.sigma, 1));
     GridBarrier hbar{0, 0, 0, 0};
-    if (hipMemcpyAsync(&hbar, ws + o_bar, sizeof(hbar), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    std::vector<uint64_t> hclk(clocks ? nclk * 2 : 0);
+    if ((clocks && hipMemcpyAsync(hclk.data(), ws + o_clk, hclk.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+        hipMemcpyAsync(&hbar, ws + o_bar, sizeof(hbar), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(hst.data(), ws + o_st, sizeof(StepState) * ns, hipMemcpyDeviceToHost, s) != hipSuccess ||
         (bp.sigma && hipMemcpyAsync(hsig.data(), sig_dev, bp.sigma * 8, hipMemcpyDeviceToHost, s) != hipSuccess))
         return fail(set_error(TTSVD_EHIP, "batch: result copy"));
@@ -736,6 +758,20 @@ int run_batch(int count, const ttsvd_tensor *X, const int *d, const int64_t *dim
         return set_error(TTSVD_EHIP, "batch: %s", hipGetErrorString(hipGetLastError()));
     }
 
+    if (clocks && bp.nrounds >= 1 && !hbar.abort) {
+        // phase durations from the device clock (time between barriers)
+        double ph[3] = {0, 0, 0};
+        for (unsigned g = 1; g <= hbar.gen && g < nclk; ++g) {
+            const int kind = (int)hclk[2 * g + 1];
+            if (kind >= 0 && kind < 3) ph[kind] += (double)(hclk[2 * g] - hclk[2 * g - 2]) * 1e-5;
+        }
+        static const char *kn[3] = {"tsqr phases", "svd phases", "tsmm phases"};
+        for (int k = 0; k < 3; ++k) {
+            char nm[96];
+            snprintf(nm, sizeof(nm), "batch_kernel: %s", kn[k]);
+            prof_add(nm, ph[k], 0.0, 0.0);
+        }
+    }
     if (hbar.abort) {
         (void)hipFree(shared->ptr);
         delete shared;

@@ -90,13 +90,17 @@ __device__ inline float dev_sqrt(float x) { return __builtin_sqrtf(x); }
 
 // ------------------------------------------------------- wave reductions
 
-// threadIdx.x behind an empty asm statement.  Values derived from it are
-// then computed where a body uses them instead of being hoisted to the start
-// of a persistent kernel, where those of every inlined body would be live at
-// once.  The statement emits no instruction.
+// threadIdx.x.  A translation unit that defines TTSVD_PERSISTENT_KERNEL (the
+// batched persistent kernel, compiled into its own code object) puts it behind
+// an empty asm statement: values derived from it are then computed where a
+// body uses them instead of being hoisted to the start of the kernel, where
+// those of every inlined body would be live at once.  The statement emits no
+// instruction.
 __device__ __forceinline__ int thread_id() {
     int t = (int)threadIdx.x;
+#ifdef TTSVD_PERSISTENT_KERNEL
     __asm__ volatile("" : "+v"(t));
+#endif
     return t;
 }
 

@@ -29,6 +29,13 @@ int plan_steps(const int64_t *dims, int d, int64_t r_max, std::vector<StepShape>
 // Keep freed stream-ordered allocations in the device's default pool.
 int keep_pool_memory(hipStream_t s);
 
+// Cooperative launch that starts only after every earlier cooperative launch
+// of the library on this device has finished (whatever its stream): two
+// grid-synchronising kernels that each hold part of the GPU while waiting for
+// the rest could otherwise wait on each other.
+hipError_t coop_launch(const void *fn, dim3 grid, dim3 block, void **args, size_t lds,
+                       hipStream_t s);
+
 // Device buffer shared by the results of one batched call: the last
 // ttsvd_tt_free of those results releases it.
 struct SharedDev {

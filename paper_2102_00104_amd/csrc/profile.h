@@ -12,5 +12,9 @@ namespace ttsvd {
 void prof_begin(hipStream_t s, const char *name, double bytes, double flops);
 // Records the matching stop event on s.
 void prof_end(hipStream_t s);
+// Whether recording is on.
+bool prof_on();
+// Adds a record measured by other means (e.g. device clocks), in ms.
+void prof_add(const char *name, double ms, double bytes, double flops);
 
 }  // namespace ttsvd

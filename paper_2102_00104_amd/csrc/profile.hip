@@ -15,8 +15,9 @@ namespace {
 
 struct Rec {
     std::string name;
-    hipEvent_t a = nullptr, b = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;  // none for records added with a duration
     double bytes = 0, flops = 0;
+    double ms = -1.0;
 };
 
 std::atomic<int> g_on{0};
@@ -37,6 +38,19 @@ hipEvent_t take_event() {
 }
 
 }  // namespace
+
+bool prof_on() { return g_on.load(std::memory_order_relaxed) != 0; }
+
+void prof_add(const char *name, double ms, double bytes, double flops) {
+    if (!prof_on()) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Rec r;
+    r.name = name;
+    r.ms = ms;
+    r.bytes = bytes;
+    r.flops = flops;
+    g_recs.push_back(r);
+}
 
 void prof_begin(hipStream_t s, const char *name, double bytes, double flops) {
     if (!g_on.load(std::memory_order_relaxed)) return;
@@ -89,13 +103,15 @@ int ttsvd_profile_read(ttsvd_kernel_stat *stats, int max_stats, int *n_stats) {
     std::map<std::string, ttsvd_kernel_stat> agg;
     std::vector<std::string> order;
     for (const Rec &r : g_recs) {
-        hipError_t e = hipEventSynchronize(r.b);
-        if (e != hipSuccess)
-            return set_error(TTSVD_EHIP, "profile_read: %s", hipGetErrorString(e));
-        float ms = 0.f;
-        e = hipEventElapsedTime(&ms, r.a, r.b);
-        if (e != hipSuccess)
-            return set_error(TTSVD_EHIP, "profile_read: %s", hipGetErrorString(e));
+        float ms = (float)r.ms;
+        if (r.ms < 0) {
+            hipError_t e = hipEventSynchronize(r.b);
+            if (e != hipSuccess)
+                return set_error(TTSVD_EHIP, "profile_read: %s", hipGetErrorString(e));
+            e = hipEventElapsedTime(&ms, r.a, r.b);
+            if (e != hipSuccess)
+                return set_error(TTSVD_EHIP, "profile_read: %s", hipGetErrorString(e));
+        }
         auto it = agg.find(r.name);
         if (it == agg.end()) {
             ttsvd_kernel_stat st;

@@ -10,6 +10,7 @@
 #include <hip/hip_cooperative_groups.h>
 
 #include "common.h"
+#include "driver.h"
 #include "kernels.h"
 #include "profile.h"
 #include "svd_dev.h"
@@ -250,10 +251,10 @@ int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma
     args[5] = &nbi;
     hipError_t e;
     switch (b.B) {
-        case 32: e = hipLaunchCooperativeKernel((const void *)svd_block_kernel<32>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
-        case 16: e = hipLaunchCooperativeKernel((const void *)svd_block_kernel<16>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
-        case 8: e = hipLaunchCooperativeKernel((const void *)svd_block_kernel<8>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
-        default: e = hipLaunchCooperativeKernel((const void *)svd_block_kernel<4>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
+        case 32: e = coop_launch((const void *)svd_block_kernel<32>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
+        case 16: e = coop_launch((const void *)svd_block_kernel<16>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
+        case 8: e = coop_launch((const void *)svd_block_kernel<8>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
+        default: e = coop_launch((const void *)svd_block_kernel<4>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
     }
     prof_end(s);
     if (e != hipSuccess)

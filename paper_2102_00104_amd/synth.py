@@ -11,6 +11,9 @@ uniformly random data with prescribed dimensions or TT ranks, Sec. 5):
 * ``uniform``  -- i.i.d. U[0, 1) entries: a full-rank, worst-case tensor.
 * ``exact_tt`` -- contraction of random Gaussian cores with prescribed ranks
   (an exact TT tensor), optionally plus i.i.d. Gaussian noise.
+* ``batch_specs`` / ``exact_tt_device`` -- the many-tensor workloads (mixed
+  shapes and ranks), assembled on the GPU because the batch is gigabytes.
+* ``serving_trace`` -- a Poisson stream of requests of log-uniform sizes.
 """
 from __future__ import annotations
 
@@ -111,3 +114,73 @@ def full_rank_workloads():
     U[0, 1) values (seed 0) viewed as d = 7, n_i = 16 and d = 28, n_i = 2,
     r_max = 32, no tolerance."""
     return [([16] * 7, 32, 0.0), ([2] * 28, 32, 0.0)]
+
+
+def batch_specs(count: int = 512, seed: int = 3, min_bytes: int = 4096,
+                max_bytes: int = 64 << 20, elem_bytes: int = 4):
+    """Shapes and bond ranks of the batched workload, ``default_rng(seed)``:
+    per tensor d ~ U{6..20} and n_i ~ U{2, 4, 8}, rejected unless
+    min_bytes <= elem_bytes * prod(n) <= max_bytes; then d - 1 bond ranks
+    ~ U{2..16}, capped.  Returns [(dims, ranks r_0..r_d)]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        d = int(rng.integers(6, 21))
+        dims = [int(x) for x in rng.choice([2, 4, 8], size=d)]
+        size = elem_bytes * prod(dims)
+        if not (min_bytes <= size <= max_bytes):
+            continue
+        inner = [int(r) for r in rng.integers(2, 17, size=d - 1)]
+        out.append((dims, capped_ranks(dims, inner)))
+    return out
+
+
+def exact_tt_device(dims: Sequence[int], ranks: Sequence[int], seed: int, noise: float,
+                    noise_seed: int, device, dtype=None):
+    """``exact_tt`` with unit-variance cores and relative noise, assembled on
+    a torch device: the cores come from ``gaussian_cores(..., seed,
+    unit_variance=True)``, the contraction runs in FP64 on the device and the
+    noise is drawn by a device generator seeded with noise_seed.  Returns the
+    flat Fortran-ordered tensor in dtype (default FP64)."""
+    import torch
+    cores = gaussian_cores(dims, ranks, seed, unit_variance=True)
+    # A Fortran (N, r) matrix is held as the row-major (r, N) tensor T.
+    T = torch.from_numpy(np.ascontiguousarray(cores[0][0].T)).to(device)
+    for G in cores[1:]:
+        r0, n, r1 = G.shape
+        Gt = torch.from_numpy(np.ascontiguousarray(G.reshape(r0, n * r1, order="F").T)).to(device)
+        T = (Gt @ T).reshape(r1, -1)
+    X = T.reshape(-1)
+    if noise > 0:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(noise_seed))
+        scale = noise * float(torch.sqrt(torch.mean(X * X)))
+        X = X + scale * torch.randn(X.numel(), generator=g, device=device, dtype=X.dtype)
+    return X if dtype is None else X.to(dtype)
+
+
+def serving_trace(duration_s: float = 10.0, rate: float = 200.0, seed: int = 4,
+                  min_exp: int = 18, max_exp: int = 30):
+    """Request trace of the serving workload, ``default_rng(seed)``: Poisson
+    arrivals at `rate` per second over `duration_s`; per request 2^e elements
+    with e ~ U{min_exp..max_exp}, split over modes with log2 n_i ~ U{1..4}
+    (drawn until they sum to e, the last one cut to fit); r_max ~ U{4..64};
+    tol log-uniform in [1e-5, 1e-2]; content bond ranks ~ U{2..16}, capped.
+    Returns [{t, dims, ranks, r_max, tol}] in arrival order."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t > duration_s:
+            break
+        e = int(rng.integers(min_exp, max_exp + 1))
+        logs = []
+        while sum(logs) < e:
+            logs.append(min(int(rng.integers(1, 5)), e - sum(logs)))
+        dims = [2 ** l for l in logs]
+        r_max = int(rng.integers(4, 65))
+        tol = float(10.0 ** rng.uniform(-5.0, -2.0))
+        inner = [int(x) for x in rng.integers(2, 17, size=len(dims) - 1)]
+        out.append(dict(t=t, dims=dims, ranks=capped_ranks(dims, inner), r_max=r_max, tol=tol))
+    return out

@@ -1,0 +1,115 @@
+"""GPU tests of the serving runtime (``ttsvd_server_*``) through the C ABI.
+
+A request's result must not depend on what it was served with: requests that
+ran in a batched launch equal ``ttsvd_decompose_batch`` of that tensor alone
+(same configuration), the others equal ``ttsvd_decompose`` -- bit for bit,
+since every work unit's arithmetic is fixed by the tensor's own plan.  The
+memory budget must never deadlock the queue, and a sample is checked against
+the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import ttcheck
+from paper_2102_00104_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU host
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2102_00104_amd as tt  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def requests():
+    """(dims, r_max, tol, X) mixing small (batchable) and large requests."""
+    out = []
+    # tolerances above the 1e-6 noise (or r_max below the exact ranks), so
+    # every kept singular value is a signal value with full relative accuracy
+    specs = [([2] * 12, 8, 1e-4), ([4, 4, 4, 4, 4], 6, 1e-4), ([16, 16, 16, 16], 40, 1e-3),
+             ([2] * 20, 16, 1e-5), ([8, 2, 8, 2, 8], 5, 0.0), ([3, 5, 7], 4, 1e-4),
+             ([16] * 5, 20, 1e-2), ([2, 4, 8, 16, 2, 4], 12, 1e-5)]
+    for i, (dims, r_max, tol) in enumerate(specs):
+        ranks = synth.capped_ranks(dims, 3 + i % 5)
+        X = synth.exact_tt_device(dims, ranks, seed=300 + i, noise=1e-6, noise_seed=400 + i,
+                                  device=DEV, dtype=torch.float64)
+        out.append((dims, r_max, tol, X))
+    return out
+
+
+def serve(reqs, **cfgkw):
+    cfg = tt.server_default_config()
+    for k, v in cfgkw.items():
+        setattr(cfg, k, v)
+    done = {}
+    with tt.Server(cfg) as srv:
+        tickets = [srv.submit(X, dims, r_max, tol) for (dims, r_max, tol, X) in reqs]
+        while len(done) < len(tickets):
+            for c in srv.poll(wait_ms=100, fetch=True, device=DEV):
+                done[c["ticket"]] = c
+        assert srv.pending() == 0
+    return [done[t] for t in tickets]
+
+
+def same(a, b):
+    assert a.ranks == b.ranks
+    for j in range(len(a.dims)):
+        assert np.array_equal(a.cores[j].cpu().numpy(), b.cores[j].cpu().numpy())
+        if j:
+            assert a.sigma[j] == b.sigma[j]
+
+
+def test_server_results_equal_alone():
+    reqs = requests()
+    res = serve(reqs, workers=3)
+    assert any(c["batch_size"] > 1 for c in res)
+    assert any(not c["batched"] for c in res)
+    cfg = tt.batch_default_config()
+    for (dims, r_max, tol, X), c in zip(reqs, res):
+        assert c["status"] == 0
+        assert c["t_submit"] <= c["t_start"] <= c["t_done"]
+        if c["batched"]:
+            alone = tt.ttsvd_decompose_batch([X], [dims], r_max, tol, cfg=cfg)[0]
+        else:
+            alone = tt.ttsvd_decompose(X, dims, r_max, tol)
+        same(c["result"], alone)
+
+
+def test_server_tiny_budget_runs_one_at_a_time():
+    reqs = requests()[:5]
+    res = serve(reqs, workers=4, hbm_budget=1)
+    assert all(c["status"] == 0 for c in res)
+    spans = sorted((c["t_start"], c["t_done"]) for c in res)
+    for (s0, e0), (s1, e1) in zip(spans, spans[1:]):
+        assert s1 >= e0 - 1e-6        # never two requests in flight
+
+
+def test_server_sequential_config_matches_oracle():
+    reqs = requests()
+    res = serve(reqs, workers=1, max_batch=1)
+    for (dims, r_max, tol, X), c in list(zip(reqs, res))[:3] + [(reqs[5], res[5])]:
+        assert c["batch_size"] == 1 and not c["batched"]
+        Xh = X.cpu().numpy()
+        o = oracle.ttsvd(Xh, dims, r_max, tol)
+        if tol > 0:
+            assert min(o.margins[1:]) > 1e-3
+        ttcheck.compare_tt(c["result"], o, Xh, tt.core_array)
+
+
+def test_server_errors():
+    X = torch.zeros(16, dtype=torch.float64, device=DEV)
+    with tt.Server() as srv:
+        with pytest.raises(tt.TTSVDError) as e:
+            srv.submit(X, [4, 4], 0, 0.0)
+        assert e.value.code == -1
+        with pytest.raises(tt.TTSVDError) as e:
+            srv.submit(X, [4, 4], 2, -1.0)
+        assert e.value.code == -1
+    bad = tt.server_default_config()
+    bad.workers = 0
+    with pytest.raises(tt.TTSVDError):
+        tt.Server(bad)
