@@ -262,6 +262,8 @@ def serve_trace(tt, trace, workers, max_batch, live_cap=48 << 30):
             X, b, i = live.pop(c["ticket"])
             live_bytes -= b
             r = c["result"]
+            if c["status"] != 0:
+                log("serving: request %d failed (%d): %s" % (i, c["status"], c["message"]))
             rec[i].update(status=c["status"], t_submit=c["t_submit"], t_start=c["t_start"],
                           t_done=c["t_done"], batch=c["batch_size"], batched=c["batched"],
                           ranks=r.ranks if r is not None else None)

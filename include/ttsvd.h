@@ -233,6 +233,7 @@ typedef struct ttsvd_completion {
     int batch_size;           /* requests in the launch that ran it                  */
     int batched;              /* 1: ran in a batched launch, 0: ttsvd_decompose      */
     double t_submit, t_start, t_done;
+    char message[160];        /* the error message when status != TTSVD_OK          */
     ttsvd_tt tt;              /* result (status TTSVD_OK); release with ttsvd_tt_free */
 } ttsvd_completion;
 

@@ -113,6 +113,7 @@ class Completion(ctypes.Structure):
         ("t_submit", ctypes.c_double),
         ("t_start", ctypes.c_double),
         ("t_done", ctypes.c_double),
+        ("message", ctypes.c_char * 160),
         ("tt", TTStruct),
     ]
 
@@ -413,7 +414,8 @@ class Server:
             item = dict(ticket=int(c.ticket), status=int(c.status), batch_size=int(c.batch_size),
                         batched=bool(c.batched),
                         t_submit=float(c.t_submit), t_start=float(c.t_start),
-                        t_done=float(c.t_done), result=None)
+                        t_done=float(c.t_done), message=c.message.decode(errors="replace"),
+                        result=None)
             if c.status == TTSVD_OK:
                 try:
                     item["result"] = _to_tt(c.tt, device, _stream(None), fetch)

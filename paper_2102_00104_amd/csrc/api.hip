@@ -92,8 +92,15 @@ Footprint footprint(const int64_t *dims, int d, int dtype, const std::vector<Ste
     for (int i = d - 1; i >= 1; --i) {
         const StepShape &s = steps[i];
         f.rbuf = std::max(f.rbuf, (size_t)(s.m * s.m));
-        f.tsqr_ws = std::max(f.tsqr_ws, tsqr_workspace_bytes(dtype, s.rows, s.m));
-        f.svd_ws = std::max(f.svd_ws, svd_scratch_bytes(s.K, s.m));
+        // The TSQR tree and the SVD scratch are not monotone in the column
+        // count (fewer columns can mean more slices or a larger Jacobi block),
+        // so size them for every rank the previous step may choose.
+        const int64_t rn_max = (i + 1 < d) ? rb[i + 1] : 1;
+        for (int64_t rn = 1; rn <= rn_max; ++rn) {
+            const int64_t m = dims[i] * rn;
+            f.tsqr_ws = std::max(f.tsqr_ws, tsqr_workspace_bytes(dtype, s.rows, m));
+            f.svd_ws = std::max(f.svd_ws, svd_scratch_bytes(std::min(s.rows, m), m));
+        }
         f.sigma_off[i] = f.sigma;
         f.sigma += (size_t)s.K;
         if (i >= 2) {
@@ -125,31 +132,52 @@ int keep_pool_memory(hipStream_t s) {
     return TTSVD_OK;
 }
 
+void *pinned_stage(size_t bytes) {
+    // (released only with the thread: the runtime may be gone by the time a
+    // thread-local destructor would run at process exit)
+    thread_local void *buf = nullptr;
+    thread_local size_t cap = 0;
+    if (bytes <= cap) return buf;
+    size_t want = std::max<size_t>(bytes, std::max<size_t>(2 * cap, 1 << 16));
+    void *p = nullptr;
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (buf) (void)hipHostFree(buf);
+    buf = p;
+    cap = want;
+    return buf;
+}
+
 hipError_t coop_launch(const void *fn, dim3 grid, dim3 block, void **args, size_t lds,
                        hipStream_t s) {
+    // A ring of events per device: an event is re-recorded only long after
+    // the waits on its previous recording were enqueued, and none is
+    // destroyed while a stream may still wait on it.
+    constexpr int kRing = 64;
     static std::mutex mu;
-    static hipEvent_t last[64] = {};
+    static hipEvent_t ring[64][kRing] = {};
+    static int next[64] = {};
+    static bool any[64] = {};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> lk(mu);
-    if (last[dev]) {
-        e = hipStreamWaitEvent(s, last[dev], 0);
+    const int prev = (next[dev] + kRing - 1) % kRing;
+    if (any[dev]) {
+        e = hipStreamWaitEvent(s, ring[dev][prev], 0);
         if (e != hipSuccess) return e;
     }
     e = hipLaunchCooperativeKernel(fn, grid, block, args, lds, s);
     if (e != hipSuccess) return e;
-    hipEvent_t ev = nullptr;
-    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(ev, s);
-    if (e != hipSuccess) {
-        (void)hipEventDestroy(ev);
-        return e;
+    hipEvent_t &ev = ring[dev][next[dev]];
+    if (!ev) {
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
     }
-    if (last[dev]) (void)hipEventDestroy(last[dev]);
-    last[dev] = ev;
+    e = hipEventRecord(ev, s);
+    if (e != hipSuccess) return e;
+    next[dev] = (next[dev] + 1) % kRing;
+    any[dev] = true;
     return hipSuccess;
 }
 
@@ -352,17 +380,22 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r
             // small SVD, rank, core T^(i)
             TTSVD_STEP_TRY(svd_launch(Rbuf, m, K, m, sig_dev + f.sigma_off[i], out->cores[i],
                                       r_max, tol, d - 1, i == d - 1, &state->step[i],
-                                      &state->step[d - 1], sv, s));
+                                      &state->step[d - 1], sv, f.svd_ws, s));
             int64_t r;
             if (tol == 0.0) {
                 r = std::min(r_max, K);
             } else {
-                StepState hs;
-                TTSVD_STEP_HIP(hipMemcpyAsync(&hs, &state->step[i], sizeof(hs), hipMemcpyDeviceToHost, s));
+                StepState *stage = (StepState *)pinned_stage(sizeof(StepState));
+                if (!stage) TTSVD_STEP_TRY(set_error(TTSVD_ENOMEM, "decompose: pinned staging"));
+                TTSVD_STEP_HIP(hipMemcpyAsync(stage, &state->step[i], sizeof(StepState), hipMemcpyDeviceToHost, s));
                 TTSVD_STEP_HIP(hipStreamSynchronize(s));
+                const StepState hs = *stage;
                 if (hs.nonfinite)
                     TTSVD_STEP_TRY(set_error(TTSVD_ENONFINITE, "decompose: non-finite sigma in step %d", i + 1));
                 r = hs.rank;
+                if (r < 1 || r > std::min(r_max, K))
+                    TTSVD_STEP_TRY(set_error(TTSVD_EHIP, "decompose: step %d: device reported rank %lld (K = %lld)",
+                                             i + 1, (long long)r, (long long)K));
             }
             ranks[i] = r;
             // W^(i-1) = reshape(W^(i) V_{:,1:r}); the last product is core T^(1)
@@ -379,12 +412,26 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r
         }
     }
 
-    TTSVD_STEP_HIP(hipMemcpyAsync(&hstate, state, sizeof(hstate), hipMemcpyDeviceToHost, s));
-    std::vector<double> sig_host(std::max<size_t>(f.sigma, 1));
+    const size_t stage_bytes = align256(sizeof(hstate)) + f.sigma * 8;
+    char *stage = (char *)pinned_stage(stage_bytes);
+    if (!stage) TTSVD_STEP_TRY(set_error(TTSVD_ENOMEM, "decompose: pinned staging"));
+    TTSVD_STEP_HIP(hipMemcpyAsync(stage, state, sizeof(hstate), hipMemcpyDeviceToHost, s));
     if (f.sigma)
-        TTSVD_STEP_HIP(hipMemcpyAsync(sig_host.data(), sig_dev, f.sigma * 8, hipMemcpyDeviceToHost, s));
+        TTSVD_STEP_HIP(hipMemcpyAsync(stage + align256(sizeof(hstate)), sig_dev, f.sigma * 8,
+                                      hipMemcpyDeviceToHost, s));
     TTSVD_STEP_HIP(hipStreamSynchronize(s));
     TTSVD_STEP_HIP(hipFreeAsync(ws, s));
+    memcpy(&hstate, stage, sizeof(hstate));
+    std::vector<double> sig_host(std::max<size_t>(f.sigma, 1));
+    if (f.sigma) memcpy(sig_host.data(), stage + align256(sizeof(hstate)), f.sigma * 8);
+    // the ranks the device reports must be the ones the steps ran with
+    for (int i = d - 1; i >= 1; --i)
+        if (hstate.step[i].rank != ranks[i]) {
+            (void)hipStreamSynchronize(s);
+            ttsvd_tt_free(out);
+            return set_error(TTSVD_EHIP, "decompose: step %d: device reported rank %lld, ran with %lld",
+                             i + 1, (long long)hstate.step[i].rank, (long long)ranks[i]);
+        }
 
     double disc_sum = 0.0;
     for (int i = d - 1; i >= 1; --i) {

@@ -654,14 +654,23 @@ int run_batch(int count, const ttsvd_tensor *X, const int *d, const int64_t *dim
     };
 
     // host image of the metadata
-    std::vector<char> img(meta, 0);
-    BTask *htask = (BTask *)(img.data() + o_task);
-    BStep *hstep = (BStep *)(img.data() + o_step);
-    double **hcptr = (double **)(img.data() + o_cptr);
-    double **hsptr = (double **)(img.data() + o_sptr);
-    int64_t *hdims = (int64_t *)(img.data() + o_dims);
+    // One pinned staging buffer (sized once: growing it could free memory a
+    // pending copy still reads) carries the metadata in and the results out.
+    const size_t r_bar = 0, r_clk = align256(sizeof(GridBarrier));
+    const size_t r_st = r_clk + align256(clocks ? nclk * 2 * 8 : 0);
+    const size_t r_sig = r_st + align256(sizeof(StepState) * ns);
+    const size_t r_end = r_sig + bp.sigma * 8;
+    char *stage = (char *)pinned_stage(std::max(meta, r_end));
+    if (!stage) return fail(set_error(TTSVD_ENOMEM, "batch: pinned staging"));
+    memset(stage, 0, meta);
+    char *img = stage;
+    BTask *htask = (BTask *)(img + o_task);
+    BStep *hstep = (BStep *)(img + o_step);
+    double **hcptr = (double **)(img + o_cptr);
+    double **hsptr = (double **)(img + o_sptr);
+    int64_t *hdims = (int64_t *)(img + o_dims);
     double *sig_dev = (double *)(ws + o_sig);
-    *(double *)(img.data() + o_one) = 1.0;
+    *(double *)(img + o_one) = 1.0;
     for (int i = 0; i < ns; ++i) {
         hcptr[i] = cores + bp.core_off[i];
         hsptr[i] = sig_dev + bp.sigma_off[i];
@@ -684,7 +693,7 @@ int run_batch(int count, const ttsvd_tensor *X, const int *d, const int64_t *dim
                        bp.dims[tk.base + i - 1]);
         }
     }
-    if (hipMemcpyAsync(ws, img.data(), meta, hipMemcpyHostToDevice, s) != hipSuccess)
+    if (hipMemcpyAsync(ws, img, meta, hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(set_error(TTSVD_EHIP, "batch: metadata copy"));
 
     // single-mode tensors: core 0 = X (no SVD), as in the single-tensor path
@@ -743,20 +752,25 @@ int run_batch(int count, const ttsvd_tensor *X, const int *d, const int64_t *dim
             return fail(set_error(TTSVD_EHIP, "batch: cooperative launch: %s", hipGetErrorString(e)));
     }
 
-    std::vector<StepState> hst(ns);
-    std::vector<double> hsig(std::max<size_t>(bp.sigma, 1));
-    GridBarrier hbar{0, 0, 0, 0};
-    std::vector<uint64_t> hclk(clocks ? nclk * 2 : 0);
-    if ((clocks && hipMemcpyAsync(hclk.data(), ws + o_clk, hclk.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) ||
-        hipMemcpyAsync(&hbar, ws + o_bar, sizeof(hbar), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(hst.data(), ws + o_st, sizeof(StepState) * ns, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        (bp.sigma && hipMemcpyAsync(hsig.data(), sig_dev, bp.sigma * 8, hipMemcpyDeviceToHost, s) != hipSuccess))
+    // (stream order: these copies run after the metadata copy read the buffer)
+    if ((clocks && hipMemcpyAsync(stage + r_clk, ws + o_clk, nclk * 2 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+        hipMemcpyAsync(stage + r_bar, ws + o_bar, sizeof(GridBarrier), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(stage + r_st, ws + o_st, sizeof(StepState) * ns, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        (bp.sigma && hipMemcpyAsync(stage + r_sig, sig_dev, bp.sigma * 8, hipMemcpyDeviceToHost, s) != hipSuccess))
         return fail(set_error(TTSVD_EHIP, "batch: result copy"));
     if (hipFreeAsync(ws, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         (void)hipFree(shared->ptr);
         delete shared;
         return set_error(TTSVD_EHIP, "batch: %s", hipGetErrorString(hipGetLastError()));
     }
+    GridBarrier hbar;
+    memcpy(&hbar, stage + r_bar, sizeof(hbar));
+    std::vector<uint64_t> hclk(clocks ? nclk * 2 : 0);
+    if (clocks) memcpy(hclk.data(), stage + r_clk, nclk * 2 * 8);
+    std::vector<StepState> hst(ns);
+    memcpy(hst.data(), stage + r_st, sizeof(StepState) * ns);
+    std::vector<double> hsig(std::max<size_t>(bp.sigma, 1));
+    if (bp.sigma) memcpy(hsig.data(), stage + r_sig, bp.sigma * 8);
 
     if (clocks && bp.nrounds >= 1 && !hbar.abort) {
         // phase durations from the device clock (time between barriers)
@@ -777,7 +791,28 @@ int run_batch(int count, const ttsvd_tensor *X, const int *d, const int64_t *dim
         delete shared;
         return set_error(TTSVD_EHIP, "batch: grid barrier timed out (workgroups not co-resident)");
     }
-    // results; a non-finite factor in any tensor fails the whole call
+    // results; a non-finite factor in any tensor fails the whole call, and so
+    // does a rank outside [1, min(r_max, K)] (the device state must be whole)
+    for (int t = 0; t < n; ++t) {
+        const BTask &tk = bp.task[t];
+        int64_t nb = 1;
+        for (int i = 0; i < tk.d; ++i) nb *= bp.dims[tk.base + i];
+        int64_t rn = 1;
+        for (int i = tk.d - 1; i >= 1; --i) {
+            const int64_t m = bp.dims[tk.base + i] * rn;
+            const int64_t rows = nb / m;
+            const int64_t K = std::min(rows, m);
+            const int64_t r = hst[tk.base + i].rank;
+            if (r < 1 || r > std::min(tk.r_max, K)) {
+                (void)hipFree(shared->ptr);
+                delete shared;
+                return set_error(TTSVD_EHIP, "batch: tensor %d step %d: device reported rank %lld (K = %lld)",
+                                 t, i + 1, (long long)r, (long long)K);
+            }
+            nb = rows * r;
+            rn = r;
+        }
+    }
     for (int t = 0; t < n; ++t) {
         const BTask &tk = bp.task[t];
         for (int i = tk.d - 1; i >= 1; --i)

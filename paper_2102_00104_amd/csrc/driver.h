@@ -29,6 +29,12 @@ int plan_steps(const int64_t *dims, int d, int64_t r_max, std::vector<StepShape>
 // Keep freed stream-ordered allocations in the device's default pool.
 int keep_pool_memory(hipStream_t s);
 
+// Pinned host staging buffer of at least `bytes` bytes owned by the calling
+// thread (grown on demand, kept for the thread's lifetime); device<->host
+// copies of results and metadata go through it, so they are plain DMA
+// transfers ordered on their stream.  NULL if the allocation fails.
+void *pinned_stage(size_t bytes);
+
 // Cooperative launch that starts only after every earlier cooperative launch
 // of the library on this device has finished (whatever its stream): two
 // grid-synchronising kernels that each hold part of the GPU while waiting for

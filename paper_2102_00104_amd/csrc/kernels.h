@@ -37,7 +37,8 @@ struct StepState {
 
 // Small SVD of the first K rows of R (m columns, column-major, ldr) by
 // one-sided Jacobi on those rows, followed by the truncation rule and the
-// core T = reshape(V_{:,1:r}^T, (r, m)).  scratch holds svd_scratch_bytes.
+// core T = reshape(V_{:,1:r}^T, (r, m)).  scratch holds scratch_bytes >=
+// svd_scratch_bytes(K, m) (checked).
 //   sigma_out: K sorted singular values (device)
 //   core_out : r x m FP64 (device), r = chosen rank, T[a + r*c] = V(c, a)
 //   first    : this is the first step (sets delta from ||Sigma||_F)
@@ -48,6 +49,7 @@ size_t svd_scratch_bytes(int64_t K, int64_t m);
 int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m,
                double *sigma_out, double *core_out,
                int64_t r_max, double tol, int dm1, int first,
-               StepState *state, StepState *state0, void *scratch, hipStream_t s);
+               StepState *state, StepState *state0, void *scratch, size_t scratch_bytes,
+               hipStream_t s);
 
 }  // namespace ttsvd

@@ -12,6 +12,7 @@
 // wake the others, so admitted work starts as soon as memory frees up; a
 // head that does not fit blocks the queue (no reordering, no starvation).
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -134,6 +135,8 @@ void worker_main(ttsvd_server *S) {
             X.stream = st;
             comp[0].status = ttsvd_decompose(&X, take[0].dims.data(), (int)take[0].dims.size(),
                                              take[0].r_max, take[0].tol, &comp[0].tt);
+            if (comp[0].status != TTSVD_OK)
+                snprintf(comp[0].message, sizeof(comp[0].message), "%s", ttsvd_last_error());
         } else {
             const int n = (int)take.size();
             std::vector<ttsvd_tensor> xs(n);
@@ -154,7 +157,10 @@ void worker_main(ttsvd_server *S) {
                                                  tl.data(), &bc, st, outs.data());
             for (int i = 0; i < n; ++i) {
                 comp[i].status = rc;
-                if (rc == TTSVD_OK) comp[i].tt = outs[i];
+                if (rc == TTSVD_OK)
+                    comp[i].tt = outs[i];
+                else
+                    snprintf(comp[i].message, sizeof(comp[i].message), "%s", ttsvd_last_error());
             }
         }
         const double t_done = now_s();

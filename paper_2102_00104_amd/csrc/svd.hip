@@ -201,9 +201,13 @@ int svd_lpp() {
 
 int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma_out,
                double *core_out, int64_t r_max, double tol, int dm1, int first,
-               StepState *state, StepState *state0, void *scratch, hipStream_t s) {
+               StepState *state, StepState *state0, void *scratch, size_t scratch_bytes,
+               hipStream_t s) {
     if (K < 1 || m < 1 || K > m || m > 4096)
         return set_error(TTSVD_EINVAL, "svd: bad shape K=%lld m=%lld", (long long)K, (long long)m);
+    if (scratch_bytes < svd_scratch_bytes(K, m))
+        return set_error(TTSVD_EINVAL, "svd: scratch %zu < %zu bytes", scratch_bytes,
+                         svd_scratch_bytes(K, m));
     if (m <= 128) {
         const int MB = m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 128;
         const int lpp = MB == 16 ? 8 : MB == 128 ? 4 : svd_lpp();

@@ -113,3 +113,20 @@ def test_server_errors():
     bad.workers = 0
     with pytest.raises(tt.TTSVDError):
         tt.Server(bad)
+
+
+@pytest.mark.parametrize("idx", [1107, 1164, 1716])
+def test_trace_requests_with_shrinking_ranks(idx):
+    # Requests of the serving trace whose ranks under tolerance fall below the
+    # upper bounds in a way that needs more TSQR tree or Jacobi scratch than
+    # the upper-bound shapes (the workspace is sized for every possible rank).
+    q = synth.serving_trace(10.0)[idx]
+    X = synth.exact_tt_device(q["dims"], q["ranks"], seed=40000 + idx, noise=1e-6,
+                              noise_seed=50000 + idx, device=DEV, dtype=torch.float32)
+    g = tt.ttsvd_decompose(X, q["dims"], q["r_max"], q["tol"])
+    assert all(1 <= r <= q["r_max"] for r in g.ranks)
+    if X.numel() <= (1 << 20):
+        Xh = X.to(torch.float64).cpu().numpy()
+        o = oracle.ttsvd(Xh, q["dims"], q["r_max"], q["tol"])
+        if min(o.margins[1:]) > 1e-2:
+            assert g.ranks == o.ranks
