@@ -135,24 +135,41 @@ __device__ void svd_epilogue(ARef A, int lda, int K, int m, double *sig, int *or
     __syncthreads();
 }
 
-// Small-matrix path, K <= m <= MB <= 128: the rows live in LDS, LPP lanes
-// work on one pair, dot products are reduced with DPP inside the group, one
-// barrier per round.  Lane `sub` of a group handles the 16-byte chunks at
-// elements 2 LPP c + 2 sub, so each LDS instruction of a group touches
-// contiguous bytes (no bank conflicts inside the group).  The first
-// MB/2 * LPP threads of the workgroup compute; any further threads only join
-// the barriers.
+// Small-matrix path, K <= m <= MB <= 128, one workgroup.  LPP lanes work on
+// one pair of rows ("slot"); lane `sub` of a slot holds the 16-byte chunks at
+// elements 2 LPP c + 2 sub of both rows in registers (E elements each), dot
+// products are reduced with DPP inside the slot.
+//
+// Ordering (recursive halving; every pair once per sweep, P - 1 rounds for
+// P = K rounded up to a power of two, zero rows beyond K): at level L the
+// rows form blocks of 2h rows, h = P / 2^(L+1); slot i (block i / h, local
+// index li = i mod h) pairs row A = block*2h + li with row
+// B = block*2h + h + (li + r) mod h in round r = 0..h-1.  Each slot keeps its
+// A row in registers for the whole level; only the B rows move, one slot
+// down per round, through their rows in LDS -- half the LDS traffic of an
+// ordering that moves both rows -- and when a block lies inside one wave the
+// round needs only a wave-level fence instead of a workgroup barrier.  At the
+// end of a level every row goes back to LDS and the next level regroups.
+// The first (P/2) * LPP threads compute; any further threads only join the
+// barriers.
 template <int MB, int LPP>
 struct SvdSmall {
-    static constexpr int NT = MB / 2 * LPP;  // computing threads
+    static constexpr int NT = MB / 2 * LPP;  // computing threads (P = MB)
     static constexpr int E = MB / LPP;       // elements per lane (E / 2 chunks of two)
     static constexpr int CS = 2 * LPP;       // elements per chunk row of a group
     static constexpr int LDA = MB + 2;       // row stride (keeps 16-byte alignment)
+    static constexpr int SPW = kWave / LPP;  // slots per wave
     static_assert(E % 2 == 0, "two elements per chunk");
     static constexpr size_t smem_bytes() {
         return sizeof(double) * (MB * LDA + MB) + sizeof(int) * (MB + 4);
     }
 };
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int MB, int LPP>
 __device__ __forceinline__ void svd_small_body(
@@ -160,15 +177,15 @@ __device__ __forceinline__ void svd_small_body(
     double *__restrict__ core_out, int64_t r_max, double tol, int dm1, int first,
     StepState *st, StepState *st0, void *smem) {
     using C = SvdSmall<MB, LPP>;
-    constexpr int NT = C::NT, E = C::E, CS = C::CS, LDA = C::LDA;
+    constexpr int E = C::E, CS = C::CS, LDA = C::LDA, SPW = C::SPW;
     double *A = reinterpret_cast<double *>(smem);
     double *sig = A + MB * LDA;
     int *order = reinterpret_cast<int *>(sig + MB);
     int *rot_count = order + MB;
     const int tid = thread_id();
     const int nth = blockDim.x;
-    const int kp = K + (K & 1);
-    const int n1 = kp - 1;
+    int P = 1;
+    while (P < K) P <<= 1;  // rows K..P-1 are zero
 
     for (int idx = tid; idx < MB * MB; idx += nth) {
         const int vv = idx / MB, e = idx % MB;
@@ -176,11 +193,22 @@ __device__ __forceinline__ void svd_small_body(
     }
     __syncthreads();
 
-    const int pi = tid / LPP;       // pair handled by this group
+    const int slot = tid / LPP;
     const int sub = tid % LPP;
-    const bool active = tid < NT && pi < kp / 2;
+    const bool active = slot < P / 2;
     const double thr = 4.0 * (double)m * 0x1p-52;
     const double thr2 = thr * thr;
+
+    auto load = [&](int row, double (&v)[E]) {
+        const double *p = A + row * LDA + 2 * sub;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = p[CS * (e / 2) + (e & 1)];
+    };
+    auto store = [&](int row, const double (&v)[E]) {
+        double *p = A + row * LDA + 2 * sub;
+#pragma unroll
+        for (int e = 0; e < E; ++e) p[CS * (e / 2) + (e & 1)] = v[e];
+    };
 
     int sweep = 0;
     for (; sweep < kMaxSweeps; ++sweep) {
@@ -188,61 +216,66 @@ __device__ __forceinline__ void svd_small_body(
         __syncthreads();
         int local = 0;
         bool big = false;
-        for (int round = 0; round < n1; ++round) {
+        for (int h = P >> 1; h >= 1; h >>= 1) {
+            const int blk = slot / h, li = slot % h;
+            const int ra = blk * 2 * h + li;
+            const int rb0 = blk * 2 * h + h;
+            const bool in_wave = h <= SPW;  // the B rows of a block never leave a wave
+            double x[E], y[E];
             if (active) {
-                int p, q;
-                if (pi == 0) {
-                    p = 0;
-                    q = 1 + round;
-                } else {
-                    int x = round + pi;
-                    x = x >= n1 ? x - n1 : x;
-                    int y = round - pi;
-                    y = y < 0 ? y + n1 : y;
-                    p = 1 + x;
-                    q = 1 + y;
-                }
-                double *ap = A + p * LDA + 2 * sub;
-                double *aq = A + q * LDA + 2 * sub;
-                double x[E], y[E];
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    x[e] = ap[CS * (e / 2) + (e & 1)];
-                    y[e] = aq[CS * (e / 2) + (e & 1)];
-                }
-                double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    al = fma(x[e], x[e], al);
-                    be = fma(y[e], y[e], be);
-                    ga = fma(x[e], y[e], ga);
-                }
-                al = group_sum<LPP>(al);
-                be = group_sum<LPP>(be);
-                ga = group_sum<LPP>(ga);
-                const double g2a = ga * ga;
-                if (g2a > thr2 * al * be && al > kTinyNorm2 && be > kTinyNorm2) {
-                    // rotation zeroing the (p, q) entry of [a_p a_q]^T [a_p a_q]:
-                    // t = 2 ga sign(be - al) / (|be - al| + sqrt((be - al)^2 + 4 ga^2)),
-                    // sign(0) = +1: the smaller root of t^2 + 2 zeta t - 1 = 0,
-                    // zeta = (be - al) / (2 ga), written without dividing by ga.
-                    const double dlt = be - al;
-                    const double g2 = ga + ga;
-                    const double h = fma(dlt, dlt, g2 * g2);
-                    const double den = fabs(dlt) + h * rsqrt_nr(h);
-                    const double t = (dlt < 0.0 ? -g2 : g2) * rcp_nr(den);
-                    const double c = rsqrt_nr(fma(t, t, 1.0));
-                    const double s = c * t;
-                    big |= g2a > kBigRel2 * al * be;
+                load(ra, x);
+                load(rb0 + li, y);
+            }
+            for (int r = 0; r < h; ++r) {
+                if (active) {
+                    double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
-                        ap[CS * (e / 2) + (e & 1)] = fma(c, x[e], -s * y[e]);
-                        aq[CS * (e / 2) + (e & 1)] = fma(s, x[e], c * y[e]);
+                        al = fma(x[e], x[e], al);
+                        be = fma(y[e], y[e], be);
+                        ga = fma(x[e], y[e], ga);
                     }
-                    local += (sub == 0);
+                    al = group_sum<LPP>(al);
+                    be = group_sum<LPP>(be);
+                    ga = group_sum<LPP>(ga);
+                    const double g2a = ga * ga;
+                    if (g2a > thr2 * al * be && al > kTinyNorm2 && be > kTinyNorm2) {
+                        // rotation zeroing the (A, B) entry of [a_A a_B]^T [a_A a_B]:
+                        // t = 2 ga sign(be - al) / (|be - al| + sqrt((be - al)^2 + 4 ga^2)),
+                        // sign(0) = +1: the smaller root of t^2 + 2 zeta t - 1 = 0,
+                        // zeta = (be - al) / (2 ga), written without dividing by ga.
+                        const double dlt = be - al;
+                        const double g2 = ga + ga;
+                        const double hh = fma(dlt, dlt, g2 * g2);
+                        const double den = fabs(dlt) + hh * rsqrt_nr(hh);
+                        const double t = (dlt < 0.0 ? -g2 : g2) * rcp_nr(den);
+                        const double c = rsqrt_nr(fma(t, t, 1.0));
+                        const double s = c * t;
+                        big |= g2a > kBigRel2 * al * be;
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            const double xe = x[e];
+                            x[e] = fma(c, xe, -s * y[e]);
+                            y[e] = fma(s, xe, c * y[e]);
+                        }
+                        local += (sub == 0);
+                    }
+                    // B moves one slot down: write it back, then take the next one
+                    store(rb0 + (li + r) % h, y);
+                }
+                if (r + 1 < h) {
+                    if (in_wave)
+                        wave_lds_sync();
+                    else
+                        __syncthreads();
+                    // the row loaded here was stored this round by the slot
+                    // above; the next round overwrites only this slot's own
+                    // row, so no second barrier is needed
+                    if (active) load(rb0 + (li + r + 1) % h, y);
                 }
             }
-            __syncthreads();
+            if (active) store(ra, x);
+            __syncthreads();  // all rows in LDS before the next level regroups them
         }
         // rot_count: groups that rotated this sweep (low 16 bits) and groups
         // that rotated a pair with relative off-diagonal above 1e-9 (high

@@ -217,13 +217,26 @@ Shape shape_for(int64_t m) {
 
 using Level = TsqrLevel;
 
+// Row tiles a slice spans at least for the wave and cooperative kernels:
+// one tile per slice gives the shortest sequential chain for small steps
+// (more, shorter tree levels); large steps are capped by the slice count
+// anyway.  TTSVD_TSQR_MIN_TILES overrides it (a tuning knob).
+int64_t min_tiles() {
+    static int64_t v = [] {
+        const char *e = getenv("TTSVD_TSQR_MIN_TILES");
+        const long x = e ? atol(e) : 1;
+        return (int64_t)((x >= 1 && x <= 64) ? x : 1);
+    }();
+    return v;
+}
+
 std::vector<Level> plan(int64_t rows, int64_t m) {
     const Shape sh = shape_for(m);
     TsqrPlanParams pp;
     if (sh.kind == Kind::Rows)
-        pp = {kMaxWaveSlices, 4};
+        pp = {kMaxWaveSlices, min_tiles()};
     else if (sh.kind == Kind::Coop)
-        pp = {kMaxCoopSlices, 4};
+        pp = {kMaxCoopSlices, min_tiles()};
     else
         pp = {kMaxColsSlices, 16};
     TsqrLevel lv[kTsqrMaxLevels];
