@@ -70,7 +70,27 @@ def kernel_profile(tt, X, dims, r_max, tol, steps):
     return stats
 
 
-def roofline_of(stats):
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/traffic_*.json), or None when there is none for this
+    kernel and workload or its sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("kernel") != kernel or rec.get("workload") != workload:
+            continue
+        h = hashlib.sha1()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() == rec["source_digest"]:
+            return float(rec["traffic_bytes_per_launch"])
+    return None
+
+
+def roofline_of(stats, workload=None):
     dom = max(stats, key=lambda s: s["total_ms"])
     secs = dom["total_ms"] / 1e3
     intensity = dom["flops"] / dom["bytes"] if dom["bytes"] else float("inf")
@@ -83,9 +103,11 @@ def roofline_of(stats):
         ach = dom["flops"] / secs / 1e12
         roof = {"bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4)}
+    traffic = measured_traffic(dom["name"], workload)
     roof.update({"kernel": dom["name"], "launches": dom["launches"],
                  "avg_launch_us": round(dom["total_ms"] * 1e3 / dom["launches"], 2),
-                 "traffic": None})
+                 "algorithmic_bytes_per_launch": round(dom["bytes"] / dom["launches"]),
+                 "traffic": round(traffic) if traffic is not None else None})
     return roof
 
 
@@ -360,6 +382,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (row slabs of the "
@@ -397,7 +421,14 @@ def main():
                 s["flops"] / (s["total_ms"] / 1e3) / 1e12 if s["total_ms"] else 0))
         results.append(dict(workload=wname, dims=dims, ranks=ranks, ms_per_step=sec * 1e3,
                             value=abytes / sec / 1e9, bytes=abytes, flops=aflops,
-                            roofline=roofline_of(stats), kernels=stats, sec=sec, res=res))
+                            roofline=roofline_of(stats, wname), kernels=stats, sec=sec, res=res))
+
+    if args.copy_calibration:
+        # a plain copy of known size: reads 2^27 doubles, writes 2^27 doubles
+        Y = torch.empty(2 ** 27, dtype=torch.float64, device=dev)
+        Y.copy_(X[: 2 ** 27])
+        torch.cuda.synchronize()
+        del Y
 
     head = results[0]
     line = {
