@@ -228,16 +228,20 @@ __device__ __forceinline__ void svd_small_body(
             }
             for (int r = 0; r < h; ++r) {
                 if (active) {
-                    double al = 0.0, be = 0.0, ga = 0.0;
+                    // two interleaved accumulators halve the dependent FMA chains
+                    double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
 #pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        al = fma(x[e], x[e], al);
-                        be = fma(y[e], y[e], be);
-                        ga = fma(x[e], y[e], ga);
+                    for (int e = 0; e < E; e += 2) {
+                        al0 = fma(x[e], x[e], al0);
+                        be0 = fma(y[e], y[e], be0);
+                        ga0 = fma(x[e], y[e], ga0);
+                        al1 = fma(x[e + 1], x[e + 1], al1);
+                        be1 = fma(y[e + 1], y[e + 1], be1);
+                        ga1 = fma(x[e + 1], y[e + 1], ga1);
                     }
-                    al = group_sum<LPP>(al);
-                    be = group_sum<LPP>(be);
-                    ga = group_sum<LPP>(ga);
+                    double al = group_sum<LPP>(al0 + al1);
+                    double be = group_sum<LPP>(be0 + be1);
+                    double ga = group_sum<LPP>(ga0 + ga1);
                     const double g2a = ga * ga;
                     if (g2a > thr2 * al * be && al > kTinyNorm2 && be > kTinyNorm2) {
                         // rotation zeroing the (A, B) entry of [a_A a_B]^T [a_A a_B]:
@@ -247,8 +251,10 @@ __device__ __forceinline__ void svd_small_body(
                         const double dlt = be - al;
                         const double g2 = ga + ga;
                         const double hh = fma(dlt, dlt, g2 * g2);
-                        const double den = fabs(dlt) + hh * rsqrt_nr(hh);
-                        const double t = (dlt < 0.0 ? -g2 : g2) * rcp_nr(den);
+                        // (t only steers the iteration: one Newton step; c must make
+                        // c^2 (1 + t^2) = 1 to working precision: two)
+                        const double den = fabs(dlt) + hh * rsqrt_nr1(hh);
+                        const double t = (dlt < 0.0 ? -g2 : g2) * rcp_nr1(den);
                         const double c = rsqrt_nr(fma(t, t, 1.0));
                         const double s = c * t;
                         big |= g2a > kBigRel2 * al * be;
