@@ -2,6 +2,9 @@
 // 2102.00104, "TSMM"): kernel and launcher; the device body and the data
 // layout are described in tsmm_dev.h.
 #include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
 
 #include "common.h"
 #include "kernels.h"
@@ -19,6 +22,111 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_kernel(
     __shared__ __attribute__((aligned(16))) char smem[tsmm_smem<KB, RPT, Tin>()];
     tsmm_body<KB, RPT, Tin, Tout>(W, rows, m, ld, V, svc, sva, k, rows_next, n_next, Y, ld_y,
                                   blockIdx.x, blockIdx.y, smem);
+}
+
+// ----------------------------------------------------------------------------
+// FP64 MFMA form for m <= 64 columns and 16 < k <= 32 output columns, where the
+// VALU kernel is limited by its FMA issue rate (I_c = 2 m k / 8 (m + k) is up
+// to ~5 flop/B).  It computes Y^T = V^T W^T with v_mfma_f64_16x16x4f64, block
+// by block of 16 rows: A = V^T (16 output columns x 4 inner), B = W^T (4 inner
+// x 16 rows), so lane l loads W(r0 + l%16, c + l/16) (16 consecutive rows of
+// 4 columns) and holds the results Y(r0 + l%16, a0 + l/16 + 4 v), v < 4
+// (stores of 16 consecutive rows per column).  All of V sits in registers;
+// W is read once.  Each wave takes 32-row blocks in a grid-stride loop.
+// ----------------------------------------------------------------------------
+typedef double tsmm_double4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaMaxM = 64;
+constexpr int kMfmaRowsPerWave = 32;
+
+template <int NT>  // 16-column output tiles (k <= 16 NT)
+__global__ __launch_bounds__(256) void tsmm_mfma_kernel(
+    const double *__restrict__ W, int64_t rows, int m, int64_t ld,
+    const double *__restrict__ V, int64_t svc, int64_t sva, int k,
+    int64_t rows_next, int64_t n_next, double *__restrict__ Y, int64_t ld_y) {
+    constexpr int KS = kMfmaMaxM / 4;  // inner steps of 4 columns of W
+    const int lane = lane_id();
+    const int lr = lane % 16, lc = lane / 16;
+    // V^T operands: A(i, kk) = V(c + kk, a0 + i), lane (i, kk) = (l % 16, l / 16)
+    double va[KS][NT];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = 4 * s + lc, a = 16 * t + lr;
+            va[s][t] = (c < m && a < k) ? V[(int64_t)c * svc + (int64_t)a * sva] : 0.0;
+        }
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + thread_id() / kWave;
+    for (int64_t r0 = wave * kMfmaRowsPerWave; r0 < rows; r0 += nwaves * kMfmaRowsPerWave) {
+        double w[2][KS];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t row = r0 + 16 * b + lr;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int c = 4 * s + lc;
+                w[b][s] = (row < rows && c < m) ? W[row + ld * c] : 0.0;
+            }
+        }
+        tsmm_double4 acc[2][NT];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[b][t] = tsmm_double4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if (4 * s < m) {  // uniform
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[b][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[s][t], w[b][s], acc[b][t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t row = r0 + 16 * b + lr;
+            if (row < rows) {
+                const int64_t q = row / rows_next;
+                const int64_t r = row - q * rows_next;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int a = 16 * t + lc + 4 * v;
+                        if (a < k) Y[r + ld_y * (q + n_next * a)] = acc[b][t][v];
+                    }
+            }
+        }
+    }
+}
+
+// TTSVD_TSMM_MFMA=0 selects the VALU kernel instead (a tuning override).
+bool tsmm_mfma_enabled() {
+    static bool v = [] {
+        const char *e = getenv("TTSVD_TSMM_MFMA");
+        return !(e && atoi(e) == 0);
+    }();
+    return v;
+}
+
+int tsmm_mfma_launch(const double *W, int64_t rows, int64_t m, int64_t ld, const double *V,
+                     int64_t svc, int64_t sva, int64_t k, int64_t n_next, double *Y,
+                     int64_t ld_y, hipStream_t s) {
+    const int64_t rows_next = rows / n_next;
+    const int64_t blocks = std::min<int64_t>(ceil_div(rows, 4 * kMfmaRowsPerWave), 4096);
+    char name[64];
+    snprintf(name, sizeof(name), "tsmm_mfma_kernel<%d>", k <= 16 ? 1 : 2);
+    prof_begin(s, name, (double)rows * m * 8.0 + (double)rows * k * 8.0, 2.0 * (double)rows * m * k);
+    if (k <= 16)
+        hipLaunchKernelGGL((tsmm_mfma_kernel<1>), dim3((unsigned)blocks), dim3(256), 0, s, W, rows,
+                           (int)m, ld, V, svc, sva, (int)k, rows_next, n_next, Y, ld_y);
+    else
+        hipLaunchKernelGGL((tsmm_mfma_kernel<2>), dim3((unsigned)blocks), dim3(256), 0, s, W, rows,
+                           (int)m, ld, V, svc, sva, (int)k, rows_next, n_next, Y, ld_y);
+    prof_end(s);
+    TTSVD_HIP_TRY(hipGetLastError());
+    return TTSVD_OK;
 }
 
 template <typename T> struct ElemName;
@@ -69,6 +177,9 @@ int tsmm_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, c
     if (ydtype == TTSVD_F64) {
         switch (dtype) {
             case TTSVD_F64:
+                if (m <= kMfmaMaxM && k > 16 && k <= 32 && tsmm_mfma_enabled())
+                    return tsmm_mfma_launch((const double *)W, rows, m, ld, V, svc, sva, k, n_next,
+                                            (double *)Y, ld_y, s);
                 return tsmm_dispatch((const double *)W, rows, m, ld, V, svc, sva, k, n_next, (double *)Y, ld_y, s);
             case TTSVD_F32:
                 return tsmm_dispatch((const float *)W, rows, m, ld, V, svc, sva, k, n_next, (double *)Y, ld_y, s);
