@@ -47,6 +47,19 @@ template <> struct Elem<bf16> {
     }
 };
 
+// *p widened to the accumulation type if ok, else zero.  p must be a valid
+// address whatever ok is (callers clamp the index): the load is then issued
+// unconditionally and the zero is a select, so the independent loads of a
+// tile stay in flight together.  (A load guarded by ok becomes a branch per
+// load, and for bf16 the widening shift inside that branch waits for the
+// load before the next one can issue.)
+template <typename Tin>
+__device__ __forceinline__ typename Elem<Tin>::acc load_or_zero(const Tin *p, bool ok) {
+    using A = typename Elem<Tin>::acc;
+    const A v = Elem<Tin>::load(p);
+    return ok ? v : A(0);
+}
+
 // Smallest positive normalized number of the accumulation type: the eps_FP
 // safeguard of the Householder reflector (Algorithm 6).
 template <typename T> struct EpsFP;

@@ -60,9 +60,10 @@ __device__ __forceinline__ void tsqr_rows_body(
         for (int i = 0; i < RPT; ++i) {
             const int64_t row = base + lane + (int64_t)kWave * i;
             const bool ok = row < r1;
+            const int64_t rc = ok ? row : r0;
 #pragma unroll
             for (int c = 0; c < M; ++c)
-                a[i][c] = (ok && c < m) ? Elem<Tin>::load(W + row + ld * c) : T(0);
+                a[i][c] = load_or_zero(W + rc + ld * (c < m ? c : 0), ok && c < m);
         }
 #pragma unroll
         for (int j = 0; j < M; ++j) {
@@ -209,10 +210,11 @@ __device__ __forceinline__ void tsqr_coop_body(
         for (int i = 0; i < RPT; ++i) {
             const int64_t row = base + lane + (int64_t)kWave * i;
             const bool ok = row < r1;
+            const int64_t rc = ok ? row : r0;
 #pragma unroll
             for (int kk = 0; kk < MW; ++kk) {
                 const int c = NW * kk + w;
-                a[i][kk] = (ok && c < m) ? Elem<Tin>::load(W + row + ld * c) : T(0);
+                a[i][kk] = load_or_zero(W + rc + ld * (c < m ? c : 0), ok && c < m);
             }
         }
         if (w == 0) reflector(std::integral_constant<int, 0>{}, 0);
