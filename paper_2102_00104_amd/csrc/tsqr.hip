@@ -45,107 +45,116 @@ __global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
 }
 
 // ----------------------------------------------------------------------------
-// Column-owner workgroup kernel, 128 < m <= 256 * CPT.
+// Column-group workgroup kernel, 128 < m <= 1024 / G.
 //
-// Thread t owns the columns t + 256 c (c < CPT) of the current NB-row tile
-// (registers) and of the workgroup's triangular factor (row-major in global
-// scratch, touched only by the owning thread).  For column j the owner builds
-// the reflector and publishes it through LDS; every thread then updates its
-// own trailing columns with in-thread dot products.
+// The 1024 threads form groups of G adjacent lanes; group k owns column k of
+// the current NB-row tile (lane q of the group holds the rows q + G i,
+// i < NBL, in registers) and column k of the workgroup's triangular factor
+// (row-major in global scratch, read and written only by lane 0 of the
+// group).  For column j the G lanes of group j build the reflector (norm
+// reduced inside the group) and publish it through LDS; every group with
+// k > j then applies it to its column: the dot product over its rows is
+// reduced inside the group, followed by the rank-1 update.  Row j + 1 of the
+// factor is fetched while step j runs (step j writes only row j), which keeps
+// the global-memory latency of the factor off the serial chain of column
+// steps.
 // ----------------------------------------------------------------------------
-constexpr int kColsThreads = 256;
+constexpr int kColsThreads = 1024;
 
-template <int CPT, int NB, typename Tin>
+template <int G, int NBL, typename Tin>
 __global__ __launch_bounds__(kColsThreads) void tsqr_cols_kernel(
     const Tin *__restrict__ W, int64_t rows, int m, int64_t ld,
     int64_t rows_per_slice, int64_t nslices, double *__restrict__ rws,
     double *__restrict__ out, int64_t ld_out, int64_t out_row0_stride,
     int kvalid) {
     using T = typename Elem<Tin>::acc;
-    __shared__ T vbuf[2][NB + 1];
+    constexpr int NB = G * NBL;
+    // vbuf[b][q NBL + i]: reflector entry of tile row q + G i (double-buffered)
+    __shared__ __attribute__((aligned(16))) T vbuf[2][NB];
+    __shared__ T vrbuf[2];
     const int tid = threadIdx.x;
+    const int k = tid / G, q = tid % G;
+    const bool col = k < m;
+    const bool lead = col && q == 0;
     const int64_t slice = blockIdx.x;
     const int64_t r0 = slice * rows_per_slice;
     const int64_t r1 = min(rows, r0 + rows_per_slice);
-    double *Rw = rws + slice * (int64_t)m * m;  // row-major: Rw[j*m + k]
+    double *Rk = rws + slice * (int64_t)m * m + (col ? k : 0);  // Rk[j m] = R(j, k)
     const T eps = EpsFP<T>::value();
 
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int k = tid + kColsThreads * c;
-        if (k < m)
-            for (int j = 0; j < m; ++j) Rw[(int64_t)j * m + k] = 0.0;
-    }
+    if (lead)
+        for (int j = 0; j < m; ++j) Rk[(int64_t)j * m] = 0.0;
 
-    T a[CPT][NB];
+    T a[NBL];
     for (int64_t base = r0; base < r1; base += NB) {
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int k = tid + kColsThreads * c;
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                const int64_t row = base + i;
-                a[c][i] = (k < m && row < r1) ? Elem<Tin>::load(W + row + ld * k) : T(0);
-            }
+        for (int i = 0; i < NBL; ++i) {
+            const int64_t row = base + q + (int64_t)G * i;
+            const bool ok = col && row < r1;
+            a[i] = load_or_zero(W + (row < r1 ? row : r0) + ld * (col ? k : 0), ok);
         }
+        double rv = lead ? Rk[0] : 0.0;  // R(j, k) at step j (lane 0 of the group)
         for (int j = 0; j < m; ++j) {
-            T *buf = vbuf[j & 1];
-            const int owner = j % kColsThreads;
-            const int cj = j / kColsThreads;
-            if (tid == owner) {
-                T x[NB];
+            const int buf = j & 1;
+            const double rnext = (lead && j + 1 < m) ? Rk[(int64_t)(j + 1) * m] : 0.0;
+            if (k == j) {
+                // reflector of column j (Algorithm 6): u = (R_jj ; tile column)
+                const T u1 = group_sum<G>(q == 0 ? (T)rv : T(0));
+                T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
 #pragma unroll
-                for (int i = 0; i < NB; ++i) {
-                    T xi = a[0][i];
-#pragma unroll
-                    for (int c = 1; c < CPT; ++c) xi = (cj == c) ? a[c][i] : xi;
-                    x[i] = xi;
+                for (int i = 0; i < NBL; i += 4) {
+                    s0 = fma(a[i], a[i], s0);
+                    if (i + 1 < NBL) s1 = fma(a[i + 1], a[i + 1], s1);
+                    if (i + 2 < NBL) s2 = fma(a[i + 2], a[i + 2], s2);
+                    if (i + 3 < NBL) s3 = fma(a[i + 3], a[i + 3], s3);
                 }
-                const T u1 = (T)Rw[(int64_t)j * m + j];
-                T s = u1 * u1;
-#pragma unroll
-                for (int i = 0; i < NB; ++i) s = fma(x[i], x[i], s);
+                T s = group_sum<G>((s0 + s1) + (s2 + s3));
+                s = fma(u1, u1, s);
                 T t = s + eps;
-                T alpha = dev_sqrt(t + eps);
+                const T t2 = t + eps;
+                T alpha = t2 * rsqrt_nr(t2);
                 alpha = (u1 > T(0)) ? -alpha : alpha;
                 t = fma(-alpha, u1, t);
-                const T beta = T(1) / dev_sqrt(t);
+                const T beta = rsqrt_nr(t);
 #pragma unroll
-                for (int i = 0; i < NB; ++i) buf[i] = beta * x[i];
-                buf[NB] = beta * (u1 - alpha);
-                Rw[(int64_t)j * m + j] = (double)alpha;
-            }
-            __syncthreads();
-            const T vr = buf[NB];
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const int k = tid + kColsThreads * c;
-                if (k > j && k < m) {
-                    double *rjk = Rw + (int64_t)j * m + k;
-                    const T rv = (T)*rjk;
-                    T g = vr * rv;
-#pragma unroll
-                    for (int i = 0; i < NB; ++i) g = fma(buf[i], a[c][i], g);
-#pragma unroll
-                    for (int i = 0; i < NB; ++i) a[c][i] = fma(-g, buf[i], a[c][i]);
-                    *rjk = (double)fma(-g, vr, rv);
+                for (int i = 0; i < NBL; ++i) vbuf[buf][q * NBL + i] = beta * a[i];
+                if (q == 0) {
+                    vrbuf[buf] = beta * (u1 - alpha);
+                    Rk[(int64_t)j * m] = (double)alpha;
                 }
             }
+            __syncthreads();
+            if (col && k > j) {
+                const T vr = vrbuf[buf];
+                const T *vb = &vbuf[buf][q * NBL];
+                T p0 = (q == 0) ? vr * (T)rv : T(0), p1 = T(0), p2 = T(0), p3 = T(0);
+#pragma unroll
+                for (int i = 0; i < NBL; i += 4) {
+                    p0 = fma(vb[i], a[i], p0);
+                    if (i + 1 < NBL) p1 = fma(vb[i + 1], a[i + 1], p1);
+                    if (i + 2 < NBL) p2 = fma(vb[i + 2], a[i + 2], p2);
+                    if (i + 3 < NBL) p3 = fma(vb[i + 3], a[i + 3], p3);
+                }
+                const T p = group_sum<G>((p0 + p1) + (p2 + p3));
+                // read the reflector from LDS again rather than keeping all
+                // NBL entries live across the reduction (register budget of
+                // a 1024-thread workgroup)
+                __asm__ volatile("" ::: "memory");
+#pragma unroll
+                for (int i = 0; i < NBL; ++i) a[i] = fma(-p, vb[i], a[i]);
+                if (q == 0) Rk[(int64_t)j * m] = (double)fma(-p, vr, (T)rv);
+            }
+            rv = rnext;
         }
         // vbuf parity restarts with the next tile: wait for all readers.
         __syncthreads();
     }
-    // Stacked output: factor row j -> out row slice*m + j (owner threads write
-    // their own columns, so no further synchronisation is needed).
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int k = tid + kColsThreads * c;
-        if (k < m)
-            for (int j = 0; j < m; ++j) {
-                const double v = (j <= k && j < kvalid) ? Rw[(int64_t)j * m + k] : 0.0;
-                out[slice * out_row0_stride + j + ld_out * k] = v;
-            }
-    }
+    // Stacked output: factor row j -> out row slice*m + j.
+    if (lead)
+        for (int j = 0; j < m; ++j) {
+            const double v = (j <= k && j < kvalid) ? Rk[(int64_t)j * m] : 0.0;
+            out[slice * out_row0_stride + j + ld_out * k] = v;
+        }
 }
 
 // ----------------------------------------------------------------------------
@@ -155,7 +164,10 @@ namespace {
 
 constexpr int64_t kMaxWaveSlices = 2048;  // single-wave slices: 256 CUs x 8 waves
 constexpr int64_t kMaxCoopSlices = 512;   // cooperative slices: up to 2 per CU
-constexpr int64_t kMaxColsSlices = 256;   // 256-thread slices: 1 per CU
+constexpr int64_t kMaxColsSlices = 256;   // 1024-thread slices: 1 per CU
+// rows per lane of the column-group kernel: 32 with one lane per column, 16
+// with two or four (register budget of a 1024-thread workgroup in FP64)
+constexpr int cols_rows_per_lane(int g) { return g == 1 ? 32 : 16; }
 
 // Kernel family and shape for m columns.
 enum class Kind { Rows, Coop, Cols };
@@ -164,7 +176,7 @@ struct Shape {
     int M;       // column bucket (Rows, Coop)
     int nw;      // waves per workgroup (Coop)
     int rpt;     // rows per lane per tile (Rows, Coop)
-    int cpt;     // columns per thread (Cols)
+    int g;       // lanes per column (Cols)
     int64_t tile;
 };
 
@@ -209,8 +221,8 @@ Shape shape_for(int64_t m) {
         sh.rpt = c.rpt;
         sh.tile = (int64_t)kWave * sh.rpt;
     } else {
-        sh.cpt = m <= 256 ? 1 : m <= 512 ? 2 : 4;
-        sh.tile = 64 / sh.cpt;
+        sh.g = m <= 256 ? 4 : m <= 512 ? 2 : 1;
+        sh.tile = (int64_t)sh.g * cols_rows_per_lane(sh.g);
     }
     return sh;
 }
@@ -238,7 +250,7 @@ std::vector<Level> plan(int64_t rows, int64_t m) {
     else if (sh.kind == Kind::Coop)
         pp = {kMaxCoopSlices, min_tiles()};
     else
-        pp = {kMaxColsSlices, 16};
+        pp = {kMaxColsSlices, 8};
     TsqrLevel lv[kTsqrMaxLevels];
     const int n = tsqr_plan_levels(rows, m, sh.tile, pp, lv);
     return std::vector<Level>(lv, lv + n);
@@ -268,7 +280,7 @@ int launch_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level 
         snprintf(name, sizeof(name), "tsqr_coop_kernel<%d, %d, %d, %s>", sh.M, sh.nw, sh.rpt,
                  tname<Tin>());
     else
-        snprintf(name, sizeof(name), "tsqr_cols_kernel<%d, %d, %s>", sh.cpt, 64 / sh.cpt, tname<Tin>());
+        snprintf(name, sizeof(name), "tsqr_cols_kernel<%d, %d, %s>", sh.g, cols_rows_per_lane(sh.g), tname<Tin>());
     prof_begin(s, name, (double)rows * (double)m * sizeof(Tin), 2.0 * (double)rows * (double)m * (double)m);
     int rc = launch_level_raw(W, rows, m, ld, l, out, ld_out, out_stride, kvalid, rws, s);
     prof_end(s);
@@ -323,23 +335,20 @@ int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Le
 #undef TTSVD_COOP_CASE
     } else {
         dim3 grid((unsigned)l.nslices), block(kColsThreads);
-        switch (sh.cpt) {
-            case 1:
-                hipLaunchKernelGGL((tsqr_cols_kernel<1, 64, Tin>), grid, block, 0, s, W, rows,
-                                   (int)m, ld, l.rows_per_slice, l.nslices, rws, out, ld_out,
-                                   out_stride, kvalid);
-                break;
-            case 2:
-                hipLaunchKernelGGL((tsqr_cols_kernel<2, 32, Tin>), grid, block, 0, s, W, rows,
-                                   (int)m, ld, l.rows_per_slice, l.nslices, rws, out, ld_out,
-                                   out_stride, kvalid);
-                break;
+#define TTSVD_COLS_CASE(GG)                                                                   \
+    case GG:                                                                                  \
+        hipLaunchKernelGGL((tsqr_cols_kernel<GG, cols_rows_per_lane(GG), Tin>), grid, block, 0, s, \
+                           W, rows, (int)m, ld, l.rows_per_slice, l.nslices, rws, out, ld_out, \
+                           out_stride, kvalid);                                               \
+        break;
+        switch (sh.g) {
+            TTSVD_COLS_CASE(1)
+            TTSVD_COLS_CASE(2)
+            TTSVD_COLS_CASE(4)
             default:
-                hipLaunchKernelGGL((tsqr_cols_kernel<4, 16, Tin>), grid, block, 0, s, W, rows,
-                                   (int)m, ld, l.rows_per_slice, l.nslices, rws, out, ld_out,
-                                   out_stride, kvalid);
-                break;
+                return set_error(TTSVD_EUNSUPPORTED, "tsqr: bad column group %d", sh.g);
         }
+#undef TTSVD_COLS_CASE
     }
     TTSVD_HIP_TRY(hipGetLastError());
     return TTSVD_OK;
