@@ -33,13 +33,20 @@ __global__ __launch_bounds__(MB / 2 * LPP) void svd_small_kernel(
 // The K rows of R (zero-padded to Kp, a multiple of 2B) are split into nb
 // blocks of B rows in a global buffer.  A sweep is a round-robin tournament
 // over the blocks (nb - 1 block rounds); in each block round workgroup g
-// takes block pair g, copies its 2B rows to LDS, runs one full inner Jacobi
-// sweep over them (2B - 1 rounds of B parallel pairs, TPP lanes per pair)
-// and writes them back.  Block rounds are separated by a grid barrier of the
+// takes block pair g, copies its 2B rows to LDS, rotates them (B parallel
+// pairs per round, TPP lanes per pair) and writes them back: a full inner
+// sweep over the 2B rows (2B - 1 rounds) in the first block round, which
+// pairs every block once, and only the B x B cross pairs (B rounds) in the
+// others, so every pair of rows meets at least once per sweep in about
+// K + B rounds.  Block rounds are separated by a grid barrier of the
 // cooperative launch; a sweep in which no rotation had a relative
-// off-diagonal above 1e-9 is the last one (quadratic convergence).
+// off-diagonal above 1e-9 is the last one (quadratic convergence).  NT
+// threads per workgroup: 1024 (B = 16 or 32, one wave or half a wave per
+// pair) where the 2B rows fit in LDS, else 256.
 // ----------------------------------------------------------------------------
 constexpr int kBlockThreads = 256;
+constexpr int kBlockThreadsWide = 1024;
+constexpr size_t kBlockWideLds = 144 * 1024;
 constexpr int kBlockMaxE = 16;  // elements per lane and vector
 
 struct BlockCtl {
@@ -47,21 +54,22 @@ struct BlockCtl {
     int sweeps;           // sweeps performed
 };
 
-template <int B>
-__global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(
+template <int B, int NT>
+__global__ __launch_bounds__(NT) void svd_block_kernel(
     const double *__restrict__ R, int64_t ldr, int K, int m, int mp, int nb,
     double *__restrict__ A, BlockCtl *ctl) {
     namespace cg = cooperative_groups;
     cg::grid_group grid = cg::this_grid();
-    constexpr int TPP = kBlockThreads / B;  // lanes per pair
+    constexpr int TPP = NT / B;  // lanes per pair
+    static_assert(TPP <= kWave && (TPP & (TPP - 1)) == 0, "pair lanes inside one wave");
     extern __shared__ __attribute__((aligned(16))) double S[];  // 2B rows of mp
     const int tid = threadIdx.x;
     const int kp = nb * B;
     const int ne = mp / TPP;  // elements per lane (even, <= kBlockMaxE)
 
     // rows of R -> A (zero padding beyond K rows and m columns)
-    for (int64_t idx = (int64_t)blockIdx.x * kBlockThreads + tid; idx < (int64_t)kp * mp;
-         idx += (int64_t)gridDim.x * kBlockThreads) {
+    for (int64_t idx = (int64_t)blockIdx.x * NT + tid; idx < (int64_t)kp * mp;
+         idx += (int64_t)gridDim.x * NT) {
         const int vv = (int)(idx / mp), e = (int)(idx % mp);
         A[idx] = (vv < K && e < m) ? R[vv + ldr * e] : 0.0;
     }
@@ -83,15 +91,26 @@ __global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(
         for (int br = 0; br < nb - 1; ++br) {
             int bp, bq;
             pair_of(br, blockIdx.x, nb, bp, bq);
-            for (int idx = tid; idx < B * mp; idx += kBlockThreads) {
+            for (int idx = tid; idx < B * mp; idx += NT) {
                 const int vv = idx / mp, e = idx % mp;
                 S[vv * mp + e] = A[(int64_t)(bp * B + vv) * mp + e];
                 S[(B + vv) * mp + e] = A[(int64_t)(bq * B + vv) * mp + e];
             }
             __syncthreads();
-            for (int round = 0; round < 2 * B - 1; ++round) {
+            // The first block round pairs every block once: a full sweep over
+            // its 2B rows also covers the pairs inside each block.  Later
+            // block rounds rotate only the B x B cross pairs (row pi of block
+            // bp with row (pi + round) mod B of block bq), so a sweep takes
+            // about K + B rounds instead of 2K.
+            const int nrounds = (br == 0) ? 2 * B - 1 : B;
+            for (int round = 0; round < nrounds; ++round) {
                 int p, q;
-                pair_of(round, pi, 2 * B, p, q);
+                if (br == 0) {
+                    pair_of(round, pi, 2 * B, p, q);
+                } else {
+                    p = pi;
+                    q = B + (pi + round) % B;
+                }
                 double *ap = S + p * mp + 2 * sub;
                 double *aq = S + q * mp + 2 * sub;
                 double x[kBlockMaxE], y[kBlockMaxE];
@@ -129,7 +148,7 @@ __global__ __launch_bounds__(kBlockThreads) void svd_block_kernel(
                 }
                 __syncthreads();
             }
-            for (int idx = tid; idx < B * mp; idx += kBlockThreads) {
+            for (int idx = tid; idx < B * mp; idx += NT) {
                 const int vv = idx / mp, e = idx % mp;
                 A[(int64_t)(bp * B + vv) * mp + e] = S[vv * mp + e];
                 A[(int64_t)(bq * B + vv) * mp + e] = S[(B + vv) * mp + e];
@@ -165,12 +184,26 @@ __global__ __launch_bounds__(1024) void svd_block_finish_kernel(
 namespace {
 
 // Block shape of the large-matrix path: B rows per block with 2 B rows of
-// mp (m rounded up to 2 TPP) in at most 64 KiB of LDS, TPP = 256 / B.
+// mp (m rounded up to 2 TPP) in LDS, TPP = nt / B: 1024 threads with
+// B = 32 or 16 in at most 144 KiB where that fits, else 256 threads in at
+// most 64 KiB.
 struct BlockShape {
-    int B, tpp, mp, nb, kp;
+    int B, tpp, mp, nb, kp, nt;
 };
 BlockShape block_shape(int64_t K, int64_t m) {
-    BlockShape b{32, 0, 0, 0, 0};
+    BlockShape b{32, 0, 0, 0, 0, kBlockThreadsWide};
+    for (int B : {32, 16}) {
+        b.B = B;
+        b.tpp = kBlockThreadsWide / B;
+        b.mp = (int)ceil_div(m, 2 * b.tpp) * 2 * b.tpp;
+        if ((size_t)2 * B * b.mp * 8 <= kBlockWideLds && b.mp / b.tpp <= kBlockMaxE) {
+            b.nb = (int)ceil_div(K, 2 * b.B) * 2;
+            b.kp = b.nb * b.B;
+            return b;
+        }
+    }
+    b.B = 32;
+    b.nt = kBlockThreads;
     for (;;) {
         b.tpp = kBlockThreads / b.B;
         b.mp = (int)ceil_div(m, 2 * b.tpp) * 2 * b.tpp;
@@ -242,7 +275,7 @@ int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma
     double *A = (double *)scratch;
     BlockCtl *ctl = (BlockCtl *)(A + (size_t)b.kp * b.mp);
     char name[64];
-    snprintf(name, sizeof(name), "svd_block_kernel<%d>", b.B);
+    snprintf(name, sizeof(name), "svd_block_kernel<%d, %d>", b.B, b.nt);
     prof_begin(s, name, (double)(m * m) * 8.0 + (double)(K * m) * 8.0, 0.0);
     const size_t lds = (size_t)2 * b.B * b.mp * sizeof(double);
     int nbk = b.nb / 2;
@@ -253,13 +286,19 @@ int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma
     args[3] = &mi;
     args[4] = &mpi;
     args[5] = &nbi;
-    hipError_t e;
-    switch (b.B) {
-        case 32: e = coop_launch((const void *)svd_block_kernel<32>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
-        case 16: e = coop_launch((const void *)svd_block_kernel<16>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
-        case 8: e = coop_launch((const void *)svd_block_kernel<8>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
-        default: e = coop_launch((const void *)svd_block_kernel<4>, dim3(nbk), dim3(kBlockThreads), args, lds, s); break;
-    }
+    const void *fn;
+    if (b.nt == kBlockThreadsWide)
+        fn = b.B == 32 ? (const void *)svd_block_kernel<32, kBlockThreadsWide>
+                       : (const void *)svd_block_kernel<16, kBlockThreadsWide>;
+    else
+        fn = b.B == 32   ? (const void *)svd_block_kernel<32, kBlockThreads>
+             : b.B == 16 ? (const void *)svd_block_kernel<16, kBlockThreads>
+             : b.B == 8  ? (const void *)svd_block_kernel<8, kBlockThreads>
+                         : (const void *)svd_block_kernel<4, kBlockThreads>;
+    hipError_t e = hipSuccess;
+    if (lds > 64 * 1024)
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) e = coop_launch(fn, dim3(nbk), dim3(b.nt), args, lds, s);
     prof_end(s);
     if (e != hipSuccess)
         return set_error(TTSVD_EHIP, "svd: cooperative launch: %s", hipGetErrorString(e));

@@ -159,6 +159,8 @@ def test_small_exact_tt_workload():
     ([2] * 12, 5, 0.0), ([2] * 12, 16, 0.0), ([3, 4, 5, 6], 4, 0.0), ([16, 16, 16], 7, 0.0),
     ([4] * 7, 10, 0.0), ([2] * 14, 32, 0.0), ([8, 8, 8, 8], 100, 0.0),
     ([16, 16, 16, 16], 40, 0.0), ([8, 8, 8, 8, 8], 24, 0.0),
+    # block Jacobi SVD with 1024-thread workgroups: 256 x 256 and 256 x 512
+    ([16] * 5, 32, 0.0),
 ])
 def test_uniform_tensors_match_oracle(dims, r_max, tol):
     log("uniform %s r=%d" % (dims, r_max))
