@@ -54,8 +54,8 @@ __global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
 // group).  For column j the G lanes of group j build the reflector (norm
 // reduced inside the group) and publish it through LDS; every group with
 // k > j then applies it to its column: the dot product over its rows is
-// reduced inside the group, followed by the rank-1 update.  Row j + 1 of the
-// factor is fetched while step j runs (step j writes only row j), which keeps
+// reduced inside the group, followed by the rank-1 update.  Rows of the
+// factor are fetched four steps ahead (step j writes only row j), which keeps
 // the global-memory latency of the factor off the serial chain of column
 // steps.
 // ----------------------------------------------------------------------------
@@ -93,10 +93,9 @@ __global__ __launch_bounds__(kColsThreads) void tsqr_cols_kernel(
             const bool ok = col && row < r1;
             a[i] = load_or_zero(W + (row < r1 ? row : r0) + ld * (col ? k : 0), ok);
         }
-        double rv = lead ? Rk[0] : 0.0;  // R(j, k) at step j (lane 0 of the group)
-        for (int j = 0; j < m; ++j) {
+        // Column step j with rv = R(j, k) (lane 0 of the group).
+        auto step = [&](const int j, const double rv) {
             const int buf = j & 1;
-            const double rnext = (lead && j + 1 < m) ? Rk[(int64_t)(j + 1) * m] : 0.0;
             if (k == j) {
                 // reflector of column j (Algorithm 6): u = (R_jj ; tile column)
                 const T u1 = group_sum<G>(q == 0 ? (T)rv : T(0));
@@ -126,25 +125,50 @@ __global__ __launch_bounds__(kColsThreads) void tsqr_cols_kernel(
             __syncthreads();
             if (col && k > j) {
                 const T vr = vrbuf[buf];
+                // The lane's NBL reflector entries are read from LDS once and
+                // kept in registers where they fit next to the tile (up to
+                // 128 bytes); otherwise they are read again for the update,
+                // which keeps a 1024-thread workgroup within its registers.
+                constexpr bool kHold = NBL * sizeof(T) <= 128;
                 const T *vb = &vbuf[buf][q * NBL];
+                T v[kHold ? NBL : 1];
+                if constexpr (kHold) {
+#pragma unroll
+                    for (int i = 0; i < NBL; ++i) v[i] = vb[i];
+                }
+                auto vi = [&](int i) -> T {
+                    if constexpr (kHold) return v[i];
+                    else return vb[i];
+                };
                 T p0 = (q == 0) ? vr * (T)rv : T(0), p1 = T(0), p2 = T(0), p3 = T(0);
 #pragma unroll
                 for (int i = 0; i < NBL; i += 4) {
-                    p0 = fma(vb[i], a[i], p0);
-                    if (i + 1 < NBL) p1 = fma(vb[i + 1], a[i + 1], p1);
-                    if (i + 2 < NBL) p2 = fma(vb[i + 2], a[i + 2], p2);
-                    if (i + 3 < NBL) p3 = fma(vb[i + 3], a[i + 3], p3);
+                    p0 = fma(vi(i), a[i], p0);
+                    if (i + 1 < NBL) p1 = fma(vi(i + 1), a[i + 1], p1);
+                    if (i + 2 < NBL) p2 = fma(vi(i + 2), a[i + 2], p2);
+                    if (i + 3 < NBL) p3 = fma(vi(i + 3), a[i + 3], p3);
                 }
                 const T p = group_sum<G>((p0 + p1) + (p2 + p3));
-                // read the reflector from LDS again rather than keeping all
-                // NBL entries live across the reduction (register budget of
-                // a 1024-thread workgroup)
-                __asm__ volatile("" ::: "memory");
+                if constexpr (!kHold) __asm__ volatile("" ::: "memory");  // re-read vb
 #pragma unroll
-                for (int i = 0; i < NBL; ++i) a[i] = fma(-p, vb[i], a[i]);
+                for (int i = 0; i < NBL; ++i) a[i] = fma(-p, vi(i), a[i]);
                 if (q == 0) Rk[(int64_t)j * m] = (double)fma(-p, vr, (T)rv);
             }
-            rv = rnext;
+        };
+        // Steps in groups of four; rows j0 + 4 .. j0 + 7 of the factor are
+        // fetched while steps j0 .. j0 + 3 run (step j writes only row j).
+        auto ldR = [&](int j) -> double { return (lead && j < m) ? Rk[(int64_t)j * m] : 0.0; };
+        double rq0 = ldR(0), rq1 = ldR(1), rq2 = ldR(2), rq3 = ldR(3);
+        for (int j0 = 0; j0 < m; j0 += 4) {
+            const double n0 = ldR(j0 + 4), n1 = ldR(j0 + 5), n2 = ldR(j0 + 6), n3 = ldR(j0 + 7);
+            step(j0, rq0);
+            if (j0 + 1 < m) step(j0 + 1, rq1);
+            if (j0 + 2 < m) step(j0 + 2, rq2);
+            if (j0 + 3 < m) step(j0 + 3, rq3);
+            rq0 = n0;
+            rq1 = n1;
+            rq2 = n2;
+            rq3 = n3;
         }
         // vbuf parity restarts with the next tile: wait for all readers.
         __syncthreads();
