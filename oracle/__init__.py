@@ -19,6 +19,12 @@ of the paper):
                      W <- reshape(W V_r).  ``variant="alg1"`` runs Algorithm 1
                      instead: full SVD of each unfolding, delta from ||X||_F,
                      W <- U_r Sigma_r.
+* ``thick_k``     -- the number k of right-most modes Algorithm 3 combines:
+                     the smallest k with m = n_{d-k+1} ... n_d >=
+                     max(m_min, r_est / f_1^min) (k = d if none).
+* ``ttsvd_thick`` -- Algorithm 3 (thick-bounds TT-SVD): Algorithm 2 on the
+                     tensor with its k right-most modes combined, then the
+                     combined core split by a TT-SVD of its own.
 * ``tt_full``     -- contraction of the TT cores back to a dense tensor
                      (the TT format, Sec. 2.1.2).
 
@@ -277,3 +283,79 @@ def rel_error(X: np.ndarray, Xt: np.ndarray) -> float:
     diff = X - Xt
     nd = float(np.sqrt(np.sum(diff * diff)))
     return nd / nx if nx > 0 else nd
+
+
+def thick_k(dims: Sequence[int], m_min: int, f1_min: float, r_est: int):
+    """Number k of right-most modes that Algorithm 3 combines, and their
+    product m: the smallest k in 1..d with m >= max(m_min, r_est / f1_min).
+
+    The first step of Algorithm 2 on the combined tensor shrinks the work
+    array by f_1 = r / m; asking for f_1 <= f1_min with r ~ r_est gives
+    m >= r_est / f1_min (the reading that reproduces Table 2).  Where no k
+    qualifies, all d modes are combined (k = d).
+    """
+    dims = [int(n) for n in dims]
+    if not dims or m_min < 1 or not (0.0 < f1_min <= 1.0) or r_est < 1:
+        raise ValueError("invalid thick-bounds arguments")
+    need = max(float(m_min), float(r_est) / float(f1_min))
+    m = 1
+    for k in range(1, len(dims) + 1):
+        m *= dims[len(dims) - k]
+        if m >= need:
+            return k, m
+    return len(dims), m
+
+
+@dataclass
+class OracleThick:
+    """Result of Algorithm 3: ``tt`` the d-mode TT decomposition, ``k`` and
+    ``m`` the combined modes and their product, ``main`` Algorithm 2 on the
+    combined tensor, ``rec`` the TT-SVD of its combined core (None if k <= 1
+    or k >= d), and ``err_bound`` an upper bound of ||X - X~||_F."""
+    tt: OracleTT
+    k: int
+    m: int
+    main: OracleTT
+    rec: Optional[OracleTT]
+    err_bound: float
+
+
+def ttsvd_thick(X: np.ndarray, dims: Sequence[int], r_max: int, tol: float,
+                m_min: int, f1_min: float, r_est: Optional[int] = None) -> OracleThick:
+    """Thick-bounds TT-SVD (Algorithm 3).
+
+    1. k, m <- thick_k(dims, m_min, f1_min, r_est or r_max);
+    2. W <- reshape(X, (n_1, ..., n_{d-k}, m)) (a reinterpretation in
+       Fortran order);
+    3. T^(1), ..., T^(d-k), Tbar <- TT-SVD(W) (Algorithm 2, r_max, tol);
+    4. the k cores of the combined modes from the TT-SVD of Tbar, read as the
+       tensor (r_{d-k} n_{d-k+1}, n_{d-k+2}, ..., n_d) with the same r_max
+       and tol; its first core (1, r n, r') is the core (r, n, r').
+    k <= 1 or k >= d is Algorithm 2 on X itself.  Since X = L Tbar with
+    ||L||_2 = sigma_1 of the combined step, ||X - X~|| <= e_main + sigma_1 e_rec,
+    e = sqrt(sum of discarded sigma^2) of each TT-SVD.
+    """
+    dims = [int(n) for n in dims]
+    d = len(dims)
+    k, m = thick_k(dims, m_min, f1_min, r_est if r_est is not None else r_max)
+    if k <= 1 or k >= d:
+        tt = ttsvd(X, dims, r_max, tol)
+        e = math.sqrt(sum(tt.discarded2[1:]))
+        return OracleThick(tt, k, m, tt, None, e)
+    dims_w = dims[:d - k] + [m]
+    main = ttsvd(X, dims_w, r_max, tol)
+    r = main.ranks[d - k]
+    Tbar = main.cores[d - k].reshape(-1, order="F")             # (r, m, 1)
+    dims_b = [r * dims[d - k]] + dims[d - k + 1:]
+    rec = ttsvd(Tbar, dims_b, r_max, tol)
+    ranks = main.ranks[:d - k + 1] + rec.ranks[1:]
+    cores = main.cores[:d - k] + \
+        [rec.cores[0].reshape(r, dims[d - k], rec.ranks[1], order="F").copy(order="F")] + \
+        rec.cores[1:]
+    sigma = main.sigma[:d - k + 1] + rec.sigma[1:]
+    disc = main.discarded2[:d - k + 1] + rec.discarded2[1:]
+    margins = main.margins[:d - k + 1] + rec.margins[1:]
+    tt = OracleTT(dims, ranks, cores, sigma, disc, main.delta, main.norm_sigma, margins)
+    s1 = float(main.sigma[d - k][0]) if main.sigma[d - k] is not None and len(main.sigma[d - k]) else 0.0
+    e = math.sqrt(sum(main.discarded2[1:])) + s1 * math.sqrt(sum(rec.discarded2[1:]))
+    return OracleThick(tt, k, m, main, rec, e)

@@ -270,3 +270,92 @@ def test_model_matches_oracle_shapes():
     X = synth.uniform(dims, seed=20)
     tt = oracle.ttsvd(X, dims, r_max=5, tol=0.0)
     assert model.no_tol_ranks(dims, 5) == tt.ranks
+
+
+# --------------------------------------------------------------- Algorithm 3
+
+def _read_table2_thick():
+    rows = []
+    with open(os.path.join(GOLDEN, "table2_thick_bounds.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            r_max, m, ranks, fs = [p.strip() for p in line.split("|")]
+            fr = []
+            for t in fs.split():
+                num, _, den = t.partition("/")
+                fr.append(float(num) / float(den or 1))
+            rows.append((int(r_max), int(m), [int(x) for x in ranks.split()], fr))
+    return rows
+
+
+@pytest.mark.parametrize("r_max,m,ranks,fs", _read_table2_thick())
+def test_table2_thick_bounds(r_max, m, ranks, fs):
+    # Table 2, thick-bounds rows: m_min = 16, f_1^min = 1/2 on a 2^d tensor
+    d = 11
+    dims = [2] * d
+    X = synth.uniform(dims, seed=19)
+    th = oracle.ttsvd_thick(X, dims, r_max=r_max, tol=0.0, m_min=16, f1_min=0.5)
+    assert th.m == m and 2 ** th.k == m
+    dw = [2] * (d - th.k) + [m]
+    dd = len(dw)
+    assert th.main.ranks[dd - len(ranks):dd] == ranks
+    got = [th.main.ranks[i - 1] / (dw[i - 1] * th.main.ranks[i]) for i in range(dd, dd - len(fs), -1)]
+    assert np.allclose(got, fs)
+
+
+def test_thick_k_extremes():
+    # one mode already wide enough: nothing is combined
+    assert oracle.thick_k([3, 100], 16, 0.5, 4) == (1, 100)
+    # no k qualifies: every mode is combined
+    assert oracle.thick_k([2, 2, 2], 64, 0.5, 4) == (3, 8)
+    for dims in ([3, 100], [2, 2, 2]):
+        X = synth.uniform(dims, seed=23)
+        th = oracle.ttsvd_thick(X, dims, r_max=4, tol=0.0, m_min=64 if dims == [2, 2, 2] else 16,
+                                f1_min=0.5)
+        tt = oracle.ttsvd(X, dims, r_max=4, tol=0.0)
+        assert th.rec is None and th.tt.ranks == tt.ranks
+        for a, b in zip(th.tt.cores, tt.cores):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dims,r_max", [([2] * 12, 16), ([2] * 10, 8), ([3, 4, 2, 2, 2, 2], 8)])
+def test_thick_equals_plain_without_inner_truncation(dims, r_max):
+    # When r_max does not cut any rank inside the combined block, Algorithm 3
+    # truncates the same unfolding as Algorithm 2 at the block boundary and
+    # splits the combined core exactly: same ranks, same singular values at
+    # and left of the boundary, same approximation.
+    X = synth.uniform(dims, seed=29)
+    th = oracle.ttsvd_thick(X, dims, r_max=r_max, tol=0.0, m_min=16, f1_min=0.5)
+    tt = oracle.ttsvd(X, dims, r_max=r_max, tol=0.0)
+    d = len(dims)
+    k = th.k
+    assert 1 < k < d
+    # no rank inside the block is cut: the exact ranks fit under r_max
+    assert all(oracle._prod(dims[j:]) <= min(r_max, oracle._prod(dims[:j]))
+               for j in range(d - k + 1, d))
+    assert th.tt.ranks == tt.ranks
+    for j in range(1, d - k + 1):
+        assert np.allclose(th.tt.sigma[j], tt.sigma[j], rtol=1e-12, atol=1e-12 * tt.sigma[j][0])
+    Xa, Xb = oracle.tt_full(th.tt.cores), oracle.tt_full(tt.cores)
+    assert np.linalg.norm(Xa - Xb) <= 1e-12 * np.linalg.norm(X)
+
+
+@pytest.mark.parametrize("dims,r_max,tol", [([3, 4, 5, 6, 2], 2, 0.0), ([2] * 10, 3, 0.0),
+                                            ([4, 4, 4, 4, 4], 50, 0.3)])
+def test_thick_error_bound_with_inner_truncation(dims, r_max, tol):
+    # ranks cut inside the combined block: the result differs from
+    # Algorithm 2, but ||X - X~|| stays below e_main + sigma_1 e_rec and the
+    # cores right of the block boundary keep orthonormal rows
+    X = synth.uniform(dims, seed=31)
+    th = oracle.ttsvd_thick(X, dims, r_max=r_max, tol=tol, m_min=16, f1_min=0.5)
+    d = len(dims)
+    assert 1 < th.k < d
+    assert sum(th.rec.discarded2[1:]) > 0                # something was cut inside
+    err = np.linalg.norm(X - oracle.tt_full(th.tt.cores))
+    assert err <= th.err_bound * (1 + 1e-12) + 1e-12
+    for j in list(range(1, d - th.k)) + list(range(d - th.k + 1, d)):
+        r, n, rn = th.tt.cores[j].shape
+        M = th.tt.cores[j].reshape(r, n * rn, order="F")
+        assert np.max(np.abs(M @ M.T - np.eye(r))) <= 1e-12
