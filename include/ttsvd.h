@@ -154,6 +154,42 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d,
                     int64_t r_max, double tol, ttsvd_tt *out);
 
 /*
+ * Thick-bounds variant (Algorithm 3, Sec. 3.2.3 "Thick-bounds variant").
+ *
+ * ttsvd_thick_bounds_k -- number k of right-most modes to combine: the
+ * smallest k in 1..d whose product m = n_{d-k+1} ... n_d satisfies
+ * m >= max(m_min, r_est / f1_min), k = d if none does (the reading of the
+ * threshold that reproduces Table 2).  dims: d host values; m_min >= 1;
+ * 0 < f1_min <= 1; r_est >= 1 (an estimate of the first TT rank, e.g. r_max).
+ * Writes k and m; errors: TTSVD_EINVAL (bad arguments, overflow of m).
+ */
+int ttsvd_thick_bounds_k(const int64_t *dims, int d, int64_t m_min, double f1_min,
+                         int64_t r_est, int *k, int64_t *m);
+
+/*
+ * ttsvd_decompose_thick -- thick-bounds TT decomposition (Algorithm 3):
+ * k, m from ttsvd_thick_bounds_k(dims, d, m_min, f1_min, r_max); Algorithm 2
+ * (ttsvd_decompose, same r_max and tol) on X read as the tensor
+ * (n_1, ..., n_{d-k}, m) -- the same memory in Fortran order -- and then on
+ * its last core Tbar, read as the tensor (r_{d-k} n_{d-k+1}, n_{d-k+2}, ...,
+ * n_d); the first core of the second decomposition is core d-k+1 of the
+ * result.  k <= 1 or k >= d is ttsvd_decompose itself.
+ *
+ * out is a d-mode result as from ttsvd_decompose: sigma[j] and discarded2[j]
+ * of the combined block's inner boundaries are those of the TT-SVD of Tbar;
+ * delta and norm_sigma are the first decomposition's; err_bound =
+ * e_1 + sigma_1 e_2 >= ||X - X~||_F, e_i = sqrt(sum of discarded sigma^2) of
+ * each decomposition and sigma_1 the largest singular value at the block
+ * boundary (X = L Tbar with ||L||_2 = sigma_1).  Without ranks cut inside the
+ * block the result equals ttsvd_decompose's up to rounding.  All work runs on
+ * X->stream, synchronised before returning; errors as ttsvd_decompose, plus
+ * TTSVD_EINVAL for bad m_min / f1_min.  Release with ttsvd_tt_free.
+ */
+int ttsvd_decompose_thick(const ttsvd_tensor *X, const int64_t *dims, int d,
+                          int64_t r_max, double tol, int64_t m_min, double f1_min,
+                          ttsvd_tt *out);
+
+/*
  * Batched form: Algorithm 2 applied independently to `count` tensors of
  * different shapes in one persistent cooperative launch.  All tensors advance
  * one TT step per round; the phases of a round (TSQR tree levels, small SVD

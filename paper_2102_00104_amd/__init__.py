@@ -33,7 +33,7 @@ EXPORTED = ["ttsvd_tsqr_r", "ttsvd_tsqr_workspace_size", "ttsvd_gemm_reshape",
             "ttsvd_batch_default_config", "ttsvd_decompose_batch", "ttsvd_batch_autotune",
             "ttsvd_server_default_config", "ttsvd_server_create", "ttsvd_server_submit",
             "ttsvd_server_poll", "ttsvd_server_pending", "ttsvd_server_destroy",
-            "ttsvd_server_clock"]
+            "ttsvd_server_clock", "ttsvd_thick_bounds_k", "ttsvd_decompose_thick"]
 
 
 class TTSVDError(RuntimeError):
@@ -141,6 +141,13 @@ def lib() -> ctypes.CDLL:
         L.ttsvd_decompose.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64), ctypes.c_int,
                                       i64, ctypes.c_double, ctypes.POINTER(TTStruct)]
         L.ttsvd_decompose.restype = ctypes.c_int
+        L.ttsvd_thick_bounds_k.argtypes = [ctypes.POINTER(i64), ctypes.c_int, i64, ctypes.c_double, i64,
+                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64)]
+        L.ttsvd_thick_bounds_k.restype = ctypes.c_int
+        L.ttsvd_decompose_thick.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64),
+                                            ctypes.c_int, i64, ctypes.c_double, i64, ctypes.c_double,
+                                            ctypes.POINTER(TTStruct)]
+        L.ttsvd_decompose_thick.restype = ctypes.c_int
         L.ttsvd_tt_free.argtypes = [ctypes.POINTER(TTStruct)]
         L.ttsvd_tt_free.restype = None
         L.ttsvd_footprint_bytes.argtypes = [ctypes.POINTER(i64), ctypes.c_int, i64, ctypes.c_int]
@@ -311,6 +318,34 @@ def ttsvd_decompose(X, dims: Sequence[int], r_max: int, tol: float, ld_last: int
     arr = (ctypes.c_int64 * d)(*dims)
     out = TTStruct()
     _check(lib().ttsvd_decompose(ctypes.byref(xs), arr, d, r_max, float(tol), ctypes.byref(out)))
+    try:
+        return _to_tt(out, X.device, st)
+    finally:
+        lib().ttsvd_tt_free(ctypes.byref(out))
+
+
+def thick_bounds_k(dims: Sequence[int], m_min: int, f1_min: float, r_est: int):
+    """``ttsvd_thick_bounds_k``: (k, m) of the thick-bounds variant."""
+    dims = [int(n) for n in dims]
+    arr = (ctypes.c_int64 * max(1, len(dims)))(*dims)
+    k = ctypes.c_int(0)
+    m = ctypes.c_int64(0)
+    _check(lib().ttsvd_thick_bounds_k(arr, len(dims), int(m_min), float(f1_min), int(r_est),
+                                      ctypes.byref(k), ctypes.byref(m)))
+    return k.value, m.value
+
+
+def ttsvd_decompose_thick(X, dims: Sequence[int], r_max: int, tol: float, m_min: int = 16,
+                          f1_min: float = 0.5, stream=None) -> TT:
+    """``ttsvd_decompose_thick`` (Algorithm 3) of the Fortran-ordered device tensor X."""
+    dims = [int(n) for n in dims]
+    d = len(dims)
+    st = _stream(stream)
+    xs = TensorStruct(X.data_ptr(), dtype_code(X), 0, st)
+    arr = (ctypes.c_int64 * d)(*dims)
+    out = TTStruct()
+    _check(lib().ttsvd_decompose_thick(ctypes.byref(xs), arr, d, r_max, float(tol), int(m_min),
+                                       float(f1_min), ctypes.byref(out)))
     try:
         return _to_tt(out, X.device, st)
     finally:

@@ -50,3 +50,20 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(tt, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         tt.lib()
+
+
+def test_thick_bounds_k_host_logic():
+    # host-only entry point (no GPU work): the Table 2 thick-bounds rows and
+    # the oracle's choice on a few other shapes
+    import oracle
+    from paper_2102_00104_amd import thick_bounds_k
+    for r_max, m in ((1, 16), (5, 16), (16, 32)):
+        assert thick_bounds_k([2] * 11, 16, 0.5, r_max) == (m.bit_length() - 1, m)
+    for dims, m_min, f1, r in (([2] * 28, 64, 0.5, 32), ([16] * 7, 64, 0.5, 32),
+                               ([3, 100], 16, 0.5, 4), ([2, 2, 2], 64, 0.5, 4),
+                               ([5, 3, 7, 2], 10, 1.0 / 3, 6)):
+        assert thick_bounds_k(dims, m_min, f1, r) == oracle.thick_k(dims, m_min, f1, r)
+    with pytest.raises(Exception):
+        thick_bounds_k([2, 2], 0, 0.5, 4)
+    with pytest.raises(Exception):
+        thick_bounds_k([2, 2], 4, 0.0, 4)
