@@ -150,6 +150,47 @@ def precision_forms(tt, X64, dims, r_max, steps, warmup, f64_sec, f64_res):
     return out
 
 
+def thick_bounds(tt, model, X, dims, r_max, steps, warmup, plain_sec, plain_res,
+                 m_min=16, f1_min=0.5):
+    """Algorithm 3 (thick bounds) on the headline tensor: the k right-most
+    modes combined (smallest k with m >= max(m_min, r_max / f1_min); m_min = 16
+    and f1_min = 1/2 are the paper's Table 2 setting), timed like the plain path
+    and checked against it at full size (same ranks; same singular values at
+    and left of the block boundary, where no rank inside the block is cut)."""
+    import torch
+    k, m = tt.thick_bounds_k(dims, m_min, f1_min, r_max)
+    for _ in range(warmup):
+        tt.ttsvd_decompose_thick(X, dims, r_max, 0.0, m_min=m_min, f1_min=f1_min)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(steps):
+        res = tt.ttsvd_decompose_thick(X, dims, r_max, 0.0, m_min=m_min, f1_min=f1_min)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    d = len(dims)
+    dims_w = list(dims[:d - k]) + [m]
+    abytes = model.algorithmic_bytes(dims_w, model.no_tol_ranks(dims_w, r_max), 8)
+    r = res.ranks[d - k]
+    dims_b = [r * dims[d - k]] + list(dims[d - k + 1:])
+    abytes += model.algorithmic_bytes(dims_b, model.no_tol_ranks(dims_b, r_max), 8)
+    plain_bytes = model.algorithmic_bytes(dims, model.no_tol_ranks(dims, r_max), 8)
+    dev = 0.0
+    for j in range(1, d - k + 1):
+        a, b = res.sigma[j], plain_res.sigma[j]
+        dev = max(dev, max(abs(x - y) for x, y in zip(a, b)) / b[0])
+    ok = res.ranks == plain_res.ranks and dev <= 1e-10
+    log("thick bounds: k=%d m=%d, %.3f ms/step (%.2fx plain), ranks %s, sigma dev %.1e" % (
+        k, m, sec * 1e3, plain_sec / sec, "equal" if res.ranks == plain_res.ranks else "DIFFER", dev))
+    return {"value": round(abytes / sec / 1e9, 2), "unit": "GB/s", "ms_per_step": round(sec * 1e3, 3),
+            "k": k, "m": m, "m_min": m_min, "f1_min": f1_min, "algorithmic_bytes": abytes,
+            "hbm_roofline_frac": round(abytes / sec / 1e9 / HBM_PEAK_GBS, 4),
+            "speedup_vs_plain": round(plain_sec / sec, 3),
+            "plain_bytes_per_time_GBs": round(plain_bytes / sec / 1e9, 2),
+            "parity_vs_plain": {"ranks_equal": res.ranks == plain_res.ranks,
+                                "max_sigma_dev_rel_sigma1": dev, "passed": ok}}
+
+
 def batched(tt, steps, warmup, count=512, parity_elems=1 << 24):
     """Many-tensor form: 512 FP32 exact-TT tensors of mixed shapes (d ~
     U{6..20}, n_i in {2, 4, 8}, 4 KiB .. 64 MiB, bond ranks U{2..16}, unit-
@@ -380,6 +421,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-thick", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -458,6 +500,9 @@ def main():
     if not args.no_precision:
         line["precision_forms"] = precision_forms(tt, X, head["dims"], args.r_max, args.steps,
                                                   args.warmup, head["sec"], head["res"])
+    if not args.no_thick:
+        line["thick_bounds"] = thick_bounds(tt, model, X, head["dims"], args.r_max, args.steps,
+                                            args.warmup, head["sec"], head["res"])
     if not args.no_batched:
         line["batched"] = batched(tt, args.steps, args.warmup)
     if not args.no_serving:
