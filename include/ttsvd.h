@@ -154,7 +154,7 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d,
                     int64_t r_max, double tol, ttsvd_tt *out);
 
 /*
- * Thick-bounds variant (Algorithm 3, Sec. 3.2.3 "Thick-bounds variant").
+ * Thick-bounds variant (Algorithm 3, Sec. 3.1.3 "Thick-bounds variant").
  *
  * ttsvd_thick_bounds_k -- number k of right-most modes to combine: the
  * smallest k in 1..d whose product m = n_{d-k+1} ... n_d satisfies
