@@ -36,14 +36,15 @@ template <> struct Elem<bf16> {
     __device__ static inline float load(const bf16 *p) {
         return __uint_as_float(static_cast<uint32_t>(p->bits) << 16);
     }
-    __device__ static inline void store(bf16 *p, float v) {
+    // bf16 bits of v: round to nearest, ties to even; NaN stays NaN (quiet bit kept)
+    __device__ static inline uint32_t bits(float v) {
         uint32_t u = __float_as_uint(v);
-        // round to nearest, ties to even; NaN stays NaN (quiet bit kept)
         uint32_t r = ((u >> 16) & 1u) + 0x7fffu;
-        uint32_t o = ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu))
-                         ? ((u >> 16) | 0x40u)
-                         : ((u + r) >> 16);
-        p->bits = static_cast<uint16_t>(o);
+        return ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) ? ((u >> 16) | 0x40u)
+                                                                      : ((u + r) >> 16);
+    }
+    __device__ static inline void store(bf16 *p, float v) {
+        p->bits = static_cast<uint16_t>(bits(v));
     }
 };
 

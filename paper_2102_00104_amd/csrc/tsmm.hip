@@ -110,6 +110,16 @@ bool tsmm_mfma_enabled() {
     return v;
 }
 
+// TTSVD_TSMM_BF16X2=0 turns the two-rows-per-lane bf16 kernel off (a tuning
+// override; both kernels give identical results).
+bool tsmm_bf16x2_enabled() {
+    static bool v = [] {
+        const char *e = getenv("TTSVD_TSMM_BF16X2");
+        return !(e && atoi(e) == 0);
+    }();
+    return v;
+}
+
 int tsmm_mfma_launch(const double *W, int64_t rows, int64_t m, int64_t ld, const double *V,
                      int64_t svc, int64_t sva, int64_t k, int64_t n_next, double *Y,
                      int64_t ld_y, hipStream_t s) {
@@ -127,6 +137,80 @@ int tsmm_mfma_launch(const double *W, int64_t rows, int64_t m, int64_t ld, const
     prof_end(s);
     TTSVD_HIP_TRY(hipGetLastError());
     return TTSVD_OK;
+}
+
+// bf16 -> bf16 product with two adjacent rows per lane: every W load and
+// every Y store moves 32 bits (two bf16 values, the lower address in the low
+// half) instead of 16.  Used when rows, ld, rows/n_next and ld_y are even and
+// W and Y are 4-byte aligned, so a pair never straddles a column or a block
+// of the reshape; the arithmetic (FP32 products, FP32 sums over the columns
+// in order, one rounding to bf16) is that of tsmm_kernel.
+template <int KB, int PPT>
+__global__ __launch_bounds__(kTsmmThreads) void tsmm_bf16x2_kernel(
+    const bf16 *__restrict__ W, int64_t rows, int m, int64_t ld, const double *__restrict__ V,
+    int64_t svc, int64_t sva, int k, int64_t rows_next, int64_t n_next, bf16 *__restrict__ Y,
+    int64_t ld_y) {
+    __shared__ float vs[kTsmmChunk][KB];
+    const int tid = threadIdx.x;
+    const int a0 = blockIdx.y * KB;
+    const int64_t base = (int64_t)blockIdx.x * kTsmmThreads * PPT * 2 + 2 * tid;
+    const uint32_t *__restrict__ W2 = reinterpret_cast<const uint32_t *>(W);
+    uint32_t *__restrict__ Y2 = reinterpret_cast<uint32_t *>(Y);
+    int64_t row[PPT];
+    bool ok[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        row[p] = base + (int64_t)2 * kTsmmThreads * p;  // even; row + 1 < rows when ok
+        ok[p] = row[p] < rows;
+    }
+    float acc[PPT][2][KB];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p)
+#pragma unroll
+        for (int a = 0; a < KB; ++a) acc[p][0][a] = acc[p][1][a] = 0.0f;
+
+    for (int c0 = 0; c0 < m; c0 += kTsmmChunk) {
+        __syncthreads();
+        for (int idx = tid; idx < kTsmmChunk * KB; idx += kTsmmThreads) {
+            const int cc = idx / KB, a = idx % KB;
+            const int c = c0 + cc, ga = a0 + a;
+            vs[cc][a] = (c < m && ga < k) ? (float)V[(int64_t)c * svc + (int64_t)ga * sva] : 0.0f;
+        }
+        __syncthreads();
+        const int nc = min(kTsmmChunk, m - c0);
+#pragma unroll 4
+        for (int cc = 0; cc < nc; ++cc) {
+            float lo[PPT], hi[PPT];
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const uint32_t u = ok[p] ? W2[(row[p] + ld * (c0 + cc)) >> 1] : 0u;
+                lo[p] = __uint_as_float(u << 16);
+                hi[p] = __uint_as_float(u & 0xffff0000u);
+            }
+#pragma unroll
+            for (int a = 0; a < KB; ++a) {
+                const float vv = vs[cc][a];
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    acc[p][0][a] = fmaf(lo[p], vv, acc[p][0][a]);
+                    acc[p][1][a] = fmaf(hi[p], vv, acc[p][1][a]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        if (!ok[p]) continue;
+        const int64_t q = row[p] / rows_next;
+        const int64_t r = row[p] - q * rows_next;  // even, r + 1 < rows_next
+#pragma unroll
+        for (int a = 0; a < KB; ++a) {
+            const int ga = a0 + a;
+            if (ga < k)
+                Y2[(r + ld_y * (q + n_next * ga)) >> 1] =
+                    Elem<bf16>::bits(acc[p][0][a]) | (Elem<bf16>::bits(acc[p][1][a]) << 16);
+        }
+    }
 }
 
 template <typename T> struct ElemName;
@@ -171,6 +255,40 @@ static int tsmm_dispatch(const Tin *W, int64_t rows, int64_t m, int64_t ld, cons
     return TTSVD_OK;
 }
 
+// bf16 -> bf16 with two rows per lane where the shapes allow it.
+static int tsmm_bf16x2_dispatch(const bf16 *W, int64_t rows, int64_t m, int64_t ld,
+                                const double *V, int64_t svc, int64_t sva, int64_t k,
+                                int64_t n_next, bf16 *Y, int64_t ld_y, hipStream_t s) {
+    const int64_t rows_next = rows / n_next;
+    const int KB = (int)cpow2((int)std::min<int64_t>(k, 64));
+    const int ky = (int)ceil_div(k, KB);
+#define TTSVD_TSMM2_CASE(KK, PP)                                                              \
+    case KK: {                                                                                \
+        dim3 grid((unsigned)ceil_div(rows, (int64_t)kTsmmThreads * 2 * PP), (unsigned)ky);    \
+        char name[64];                                                                        \
+        snprintf(name, sizeof(name), "tsmm_bf16x2_kernel<%d, %d>", KK, PP);                  \
+        prof_begin(s, name, (double)rows * m * 2 + (double)rows * k * 2, 2.0 * (double)rows * m * k); \
+        hipLaunchKernelGGL((tsmm_bf16x2_kernel<KK, PP>), grid, dim3(kTsmmThreads), 0, s, W,   \
+                           rows, (int)m, ld, V, svc, sva, (int)k, rows_next, n_next, Y, ld_y); \
+        prof_end(s);                                                                          \
+        break;                                                                                \
+    }
+    switch (KB) {
+        TTSVD_TSMM2_CASE(1, 4)
+        TTSVD_TSMM2_CASE(2, 4)
+        TTSVD_TSMM2_CASE(4, 4)
+        TTSVD_TSMM2_CASE(8, 2)
+        TTSVD_TSMM2_CASE(16, 2)
+        TTSVD_TSMM2_CASE(32, 1)
+        TTSVD_TSMM2_CASE(64, 1)
+        default:
+            return set_error(TTSVD_EUNSUPPORTED, "tsmm: k bucket %d", KB);
+    }
+#undef TTSVD_TSMM2_CASE
+    TTSVD_HIP_TRY(hipGetLastError());
+    return TTSVD_OK;
+}
+
 int tsmm_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, const double *V,
                 int64_t svc, int64_t sva, int64_t k, int64_t n_next, void *Y, int ydtype,
                 int64_t ld_y, hipStream_t s) {
@@ -191,6 +309,10 @@ int tsmm_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, c
             case TTSVD_F32:
                 return tsmm_dispatch((const float *)W, rows, m, ld, V, svc, sva, k, n_next, (float *)Y, ld_y, s);
             case TTSVD_BF16:
+                if (rows % 2 == 0 && ld % 2 == 0 && (rows / n_next) % 2 == 0 && ld_y % 2 == 0 &&
+                    ((uintptr_t)W & 3) == 0 && ((uintptr_t)Y & 3) == 0 && tsmm_bf16x2_enabled())
+                    return tsmm_bf16x2_dispatch((const bf16 *)W, rows, m, ld, V, svc, sva, k,
+                                                n_next, (bf16 *)Y, ld_y, s);
                 return tsmm_dispatch((const bf16 *)W, rows, m, ld, V, svc, sva, k, n_next, (bf16 *)Y, ld_y, s);
         }
     }
