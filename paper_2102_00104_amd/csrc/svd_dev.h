@@ -157,7 +157,17 @@ struct SvdSmall {
     static constexpr int NT = MB / 2 * LPP;  // computing threads (P = MB)
     static constexpr int E = MB / LPP;       // elements per lane (E / 2 chunks of two)
     static constexpr int CS = 2 * LPP;       // elements per chunk row of a group
-    static constexpr int LDA = MB + 2;       // row stride (keeps 16-byte alignment)
+    // Row stride in doubles: the smallest >= MB with LDA = 2 LPP (mod 32).  A
+    // 16-lane pass of a 16-byte LDS access covers 16 / LPP slots of LPP lanes
+    // (16 LPP bytes each) on consecutive rows; rows 16 LPP bytes apart modulo
+    // the 256 bytes of the 64 banks put those slots on disjoint banks.  (Even,
+    // so rows stay 16-byte aligned.)
+    static constexpr int lda() {
+        int l = MB;
+        while (l % 32 != (2 * LPP) % 32) ++l;
+        return l;
+    }
+    static constexpr int LDA = lda();
     static constexpr int SPW = kWave / LPP;  // slots per wave
     static_assert(E % 2 == 0, "two elements per chunk");
     static constexpr size_t smem_bytes() {
@@ -217,7 +227,9 @@ __device__ __forceinline__ void svd_small_body(
         int local = 0;
         bool big = false;
         for (int h = P >> 1; h >= 1; h >>= 1) {
-            const int blk = slot / h, li = slot % h;
+            // h is a power of two: shifts and masks, no integer division
+            const int lh = __builtin_ctz(h);
+            const int blk = slot >> lh, li = slot & (h - 1);
             const int ra = blk * 2 * h + li;
             const int rb0 = blk * 2 * h + h;
             const bool in_wave = h <= SPW;  // the B rows of a block never leave a wave
@@ -267,7 +279,7 @@ __device__ __forceinline__ void svd_small_body(
                         local += (sub == 0);
                     }
                     // B moves one slot down: write it back, then take the next one
-                    store(rb0 + (li + r) % h, y);
+                    store(rb0 + ((li + r) & (h - 1)), y);
                 }
                 if (r + 1 < h) {
                     if (in_wave)
@@ -277,7 +289,7 @@ __device__ __forceinline__ void svd_small_body(
                     // the row loaded here was stored this round by the slot
                     // above; the next round overwrites only this slot's own
                     // row, so no second barrier is needed
-                    if (active) load(rb0 + (li + r + 1) % h, y);
+                    if (active) load(rb0 + ((li + r + 1) & (h - 1)), y);
                 }
             }
             if (active) store(ra, x);
