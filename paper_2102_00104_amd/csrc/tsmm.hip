@@ -110,11 +110,11 @@ bool tsmm_mfma_enabled() {
     return v;
 }
 
-// TTSVD_TSMM_BF16X2=0 turns the two-rows-per-lane bf16 kernel off (a tuning
+// TTSVD_TSMM_X2=0 turns the two-rows-per-lane kernels off (a tuning
 // override; both kernels give identical results).
-bool tsmm_bf16x2_enabled() {
+bool tsmm_x2_enabled() {
     static bool v = [] {
-        const char *e = getenv("TTSVD_TSMM_BF16X2");
+        const char *e = getenv("TTSVD_TSMM_X2");
         return !(e && atoi(e) == 0);
     }();
     return v;
@@ -139,23 +139,48 @@ int tsmm_mfma_launch(const double *W, int64_t rows, int64_t m, int64_t ld, const
     return TTSVD_OK;
 }
 
-// bf16 -> bf16 product with two adjacent rows per lane: every W load and
-// every Y store moves 32 bits (two bf16 values, the lower address in the low
-// half) instead of 16.  Used when rows, ld, rows/n_next and ld_y are even and
-// W and Y are 4-byte aligned, so a pair never straddles a column or a block
-// of the reshape; the arithmetic (FP32 products, FP32 sums over the columns
-// in order, one rounding to bf16) is that of tsmm_kernel.
-template <int KB, int PPT>
-__global__ __launch_bounds__(kTsmmThreads) void tsmm_bf16x2_kernel(
-    const bf16 *__restrict__ W, int64_t rows, int m, int64_t ld, const double *__restrict__ V,
-    int64_t svc, int64_t sva, int k, int64_t rows_next, int64_t n_next, bf16 *__restrict__ Y,
+// Two adjacent rows of one column as one memory word: bf16 pairs in 32 bits,
+// FP32 pairs in 64 bits (the lower address in the low half).
+template <typename E> struct RowPair;
+template <> struct RowPair<bf16> {
+    using word = uint32_t;
+    __device__ static inline void split(word u, float &lo, float &hi) {
+        lo = __uint_as_float(u << 16);
+        hi = __uint_as_float(u & 0xffff0000u);
+    }
+    __device__ static inline word join(float lo, float hi) {
+        return Elem<bf16>::bits(lo) | (Elem<bf16>::bits(hi) << 16);
+    }
+};
+template <> struct RowPair<float> {
+    using word = uint64_t;
+    __device__ static inline void split(word u, float &lo, float &hi) {
+        lo = __uint_as_float((uint32_t)u);
+        hi = __uint_as_float((uint32_t)(u >> 32));
+    }
+    __device__ static inline word join(float lo, float hi) {
+        return (word)__float_as_uint(lo) | ((word)__float_as_uint(hi) << 32);
+    }
+};
+
+// E -> E product (E = bf16 or FP32) with two adjacent rows per lane: every W
+// load and every Y store moves one RowPair word instead of two single
+// elements.  Used when rows, ld, rows/n_next and ld_y are even and W and Y
+// are aligned to the word, so a pair never straddles a column or a block of
+// the reshape; the arithmetic (FP32 products, FP32 sums over the columns in
+// order, one rounding to the storage type) is that of tsmm_kernel.
+template <int KB, int PPT, typename E>
+__global__ __launch_bounds__(kTsmmThreads) void tsmm_x2_kernel(
+    const E *__restrict__ W, int64_t rows, int m, int64_t ld, const double *__restrict__ V,
+    int64_t svc, int64_t sva, int k, int64_t rows_next, int64_t n_next, E *__restrict__ Y,
     int64_t ld_y) {
+    using P = RowPair<E>;
     __shared__ float vs[kTsmmChunk][KB];
     const int tid = threadIdx.x;
     const int a0 = blockIdx.y * KB;
     const int64_t base = (int64_t)blockIdx.x * kTsmmThreads * PPT * 2 + 2 * tid;
-    const uint32_t *__restrict__ W2 = reinterpret_cast<const uint32_t *>(W);
-    uint32_t *__restrict__ Y2 = reinterpret_cast<uint32_t *>(Y);
+    const typename P::word *__restrict__ W2 = reinterpret_cast<const typename P::word *>(W);
+    typename P::word *__restrict__ Y2 = reinterpret_cast<typename P::word *>(Y);
     int64_t row[PPT];
     bool ok[PPT];
 #pragma unroll
@@ -183,9 +208,9 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_bf16x2_kernel(
             float lo[PPT], hi[PPT];
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
-                const uint32_t u = ok[p] ? W2[(row[p] + ld * (c0 + cc)) >> 1] : 0u;
-                lo[p] = __uint_as_float(u << 16);
-                hi[p] = __uint_as_float(u & 0xffff0000u);
+                const typename P::word u = ok[p] ? W2[(row[p] + ld * (c0 + cc)) >> 1]
+                                                 : (typename P::word)0;
+                P::split(u, lo[p], hi[p]);
             }
 #pragma unroll
             for (int a = 0; a < KB; ++a) {
@@ -206,9 +231,7 @@ __global__ __launch_bounds__(kTsmmThreads) void tsmm_bf16x2_kernel(
 #pragma unroll
         for (int a = 0; a < KB; ++a) {
             const int ga = a0 + a;
-            if (ga < k)
-                Y2[(r + ld_y * (q + n_next * ga)) >> 1] =
-                    Elem<bf16>::bits(acc[p][0][a]) | (Elem<bf16>::bits(acc[p][1][a]) << 16);
+            if (ga < k) Y2[(r + ld_y * (q + n_next * ga)) >> 1] = P::join(acc[p][0][a], acc[p][1][a]);
         }
     }
 }
@@ -255,10 +278,11 @@ static int tsmm_dispatch(const Tin *W, int64_t rows, int64_t m, int64_t ld, cons
     return TTSVD_OK;
 }
 
-// bf16 -> bf16 with two rows per lane where the shapes allow it.
-static int tsmm_bf16x2_dispatch(const bf16 *W, int64_t rows, int64_t m, int64_t ld,
-                                const double *V, int64_t svc, int64_t sva, int64_t k,
-                                int64_t n_next, bf16 *Y, int64_t ld_y, hipStream_t s) {
+// E -> E with two rows per lane where the shapes allow it.
+template <typename E>
+static int tsmm_x2_dispatch(const E *W, int64_t rows, int64_t m, int64_t ld, const double *V,
+                            int64_t svc, int64_t sva, int64_t k, int64_t n_next, E *Y,
+                            int64_t ld_y, hipStream_t s) {
     const int64_t rows_next = rows / n_next;
     const int KB = (int)cpow2((int)std::min<int64_t>(k, 64));
     const int ky = (int)ceil_div(k, KB);
@@ -266,9 +290,10 @@ static int tsmm_bf16x2_dispatch(const bf16 *W, int64_t rows, int64_t m, int64_t 
     case KK: {                                                                                \
         dim3 grid((unsigned)ceil_div(rows, (int64_t)kTsmmThreads * 2 * PP), (unsigned)ky);    \
         char name[64];                                                                        \
-        snprintf(name, sizeof(name), "tsmm_bf16x2_kernel<%d, %d>", KK, PP);                  \
-        prof_begin(s, name, (double)rows * m * 2 + (double)rows * k * 2, 2.0 * (double)rows * m * k); \
-        hipLaunchKernelGGL((tsmm_bf16x2_kernel<KK, PP>), grid, dim3(kTsmmThreads), 0, s, W,   \
+        snprintf(name, sizeof(name), "tsmm_x2_kernel<%d, %d, %s>", KK, PP, ElemName<E>::get()); \
+        prof_begin(s, name, (double)rows * m * sizeof(E) + (double)rows * k * sizeof(E),      \
+                   2.0 * (double)rows * m * k);                                               \
+        hipLaunchKernelGGL((tsmm_x2_kernel<KK, PP, E>), grid, dim3(kTsmmThreads), 0, s, W,    \
                            rows, (int)m, ld, V, svc, sva, (int)k, rows_next, n_next, Y, ld_y); \
         prof_end(s);                                                                          \
         break;                                                                                \
@@ -289,6 +314,15 @@ static int tsmm_bf16x2_dispatch(const bf16 *W, int64_t rows, int64_t m, int64_t 
     return TTSVD_OK;
 }
 
+// Shapes and alignment that let tsmm_x2_kernel run (word = 2 elements).
+template <typename E>
+static bool x2_fits(const void *W, int64_t rows, int64_t ld, int64_t n_next, const void *Y,
+                    int64_t ld_y) {
+    const uintptr_t wmask = 2 * sizeof(E) - 1;
+    return rows % 2 == 0 && ld % 2 == 0 && (rows / n_next) % 2 == 0 && ld_y % 2 == 0 &&
+           ((uintptr_t)W & wmask) == 0 && ((uintptr_t)Y & wmask) == 0 && tsmm_x2_enabled();
+}
+
 int tsmm_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, const double *V,
                 int64_t svc, int64_t sva, int64_t k, int64_t n_next, void *Y, int ydtype,
                 int64_t ld_y, hipStream_t s) {
@@ -307,12 +341,13 @@ int tsmm_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, c
     } else if (ydtype == dtype) {
         switch (dtype) {
             case TTSVD_F32:
+                // (FP32 pairs in 64-bit words were measured slower than one
+                // 32-bit element per lane: the pair kernel is bf16-only)
                 return tsmm_dispatch((const float *)W, rows, m, ld, V, svc, sva, k, n_next, (float *)Y, ld_y, s);
             case TTSVD_BF16:
-                if (rows % 2 == 0 && ld % 2 == 0 && (rows / n_next) % 2 == 0 && ld_y % 2 == 0 &&
-                    ((uintptr_t)W & 3) == 0 && ((uintptr_t)Y & 3) == 0 && tsmm_bf16x2_enabled())
-                    return tsmm_bf16x2_dispatch((const bf16 *)W, rows, m, ld, V, svc, sva, k,
-                                                n_next, (bf16 *)Y, ld_y, s);
+                if (x2_fits<bf16>(W, rows, ld, n_next, Y, ld_y))
+                    return tsmm_x2_dispatch((const bf16 *)W, rows, m, ld, V, svc, sva, k, n_next,
+                                            (bf16 *)Y, ld_y, s);
                 return tsmm_dispatch((const bf16 *)W, rows, m, ld, V, svc, sva, k, n_next, (bf16 *)Y, ld_y, s);
         }
     }

@@ -65,7 +65,7 @@ def test_tsqr_low_precision(name, rows, cols):
 
 @pytest.mark.parametrize("name", ["f32", "bf16"])
 @pytest.mark.parametrize("rows,cols,k,n_next", [
-    (8192, 16, 16, 4),      # bf16: two rows per lane (even rows, ld, rows/n_next, ld_y)
+    (8192, 16, 16, 4),      # two rows per lane (even rows, ld, rows/n_next, ld_y)
     (65536, 64, 32, 2),     # the d = 28 shape, k bucket 32
     (1000, 7, 5, 5),        # k bucket 8, several chunks of rows per block
     (8190, 16, 16, 2),      # rows/n_next odd: one row per lane
