@@ -183,7 +183,9 @@ int ttsvd_thick_bounds_k(const int64_t *dims, int d, int64_t m_min, double f1_mi
  * boundary (X = L Tbar with ||L||_2 = sigma_1).  Without ranks cut inside the
  * block the result equals ttsvd_decompose's up to rounding.  All work runs on
  * X->stream, synchronised before returning; errors as ttsvd_decompose, plus
- * TTSVD_EINVAL for bad m_min / f1_min.  Release with ttsvd_tt_free.
+ * TTSVD_EINVAL for bad m_min / f1_min and TTSVD_EUNSUPPORTED for a padded
+ * last-mode stride (X->ld_last other than 0 or n_1 ... n_{d-1}) when modes are
+ * combined.  Release with ttsvd_tt_free.
  */
 int ttsvd_decompose_thick(const ttsvd_tensor *X, const int64_t *dims, int d,
                           int64_t r_max, double tol, int64_t m_min, double f1_min,

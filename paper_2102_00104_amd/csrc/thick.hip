@@ -50,6 +50,14 @@ int ttsvd_decompose_thick(const ttsvd_tensor *X, const int64_t *dims, int d, int
     int rc = ttsvd_thick_bounds_k(dims, d, m_min, f1_min, r_max < 1 ? 1 : r_max, &k, &m);
     if (rc != TTSVD_OK) return rc;
     if (k <= 1 || k >= d) return ttsvd_decompose(X, dims, d, r_max, tol, out);
+    // Combining the last k modes reinterprets X as (n_1 ... n_{d-k}) x m only
+    // when the last mode is stored without padding.
+    int64_t lead = 1;
+    for (int i = 0; i < d - 1; ++i) lead *= dims[i];
+    if (X->ld_last != 0 && X->ld_last != lead)
+        return set_error(TTSVD_EUNSUPPORTED,
+                         "thick: a padded last-mode stride (ld_last = %lld) cannot be combined",
+                         (long long)X->ld_last);
 
     // 1. Algorithm 2 on (n_1, ..., n_{d-k}, m): the same memory in Fortran order
     const int da = d - k + 1;

@@ -103,6 +103,20 @@ def test_thick_without_split_is_plain(dims, m_min):
         assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
+def test_thick_rejects_padded_last_mode():
+    # [2]*8 with m_min 16 combines 4 modes; a padded last-mode stride is not
+    # a reinterpretation of the combined modes
+    import ctypes
+    dims = [2] * 8
+    X = torch.zeros(2 * 160, dtype=torch.float64, device=DEV)
+    xs = tt.TensorStruct(X.data_ptr(), tt.TTSVD_F64, 160, 0)
+    arr = (ctypes.c_int64 * 8)(*dims)
+    out = tt.TTStruct()
+    rc = tt.lib().ttsvd_decompose_thick(ctypes.byref(xs), arr, 8, 4, 0.0, 16, 0.5, ctypes.byref(out))
+    assert rc == -5  # TTSVD_EUNSUPPORTED
+    assert out.priv is None
+
+
 def test_thick_errors():
     X = torch.zeros(16, dtype=torch.float64, device=DEV)
     with pytest.raises(tt.TTSVDError) as e:
