@@ -154,6 +154,50 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d,
                     int64_t r_max, double tol, ttsvd_tt *out);
 
 /*
+ * Caller-provided buffers for ttsvd_decompose (Algorithm 2, whose REQUIRE /
+ * ENSURE clauses fix the inputs and outputs; the buffers are only where the
+ * intermediate unfoldings W^(i) and the cores T^(i) live).
+ *
+ * ttsvd_workspace_size -- bytes of device workspace a decomposition of a
+ * tensor with these dims, r_max and element type needs: the two ping-pong
+ * work matrices W^(i) (sized for the rank upper bounds min(r_max, ...)), the
+ * triangular factor R, the TSQR reduction tree, the SVD scratch, the singular
+ * values and the per-step device state.  0 for invalid arguments.
+ *
+ * ttsvd_cores_size -- FP64 values the cores need at the rank upper bounds:
+ * sum_j r_{j-1} n_j r_j with r_j = min(r_max, n_1...n_j, n_{j+1}...n_d, ...)
+ * as the no-tolerance rule gives them.  0 for invalid arguments.
+ */
+size_t ttsvd_workspace_size(const int64_t *dims, int d, int64_t r_max, int dtype);
+size_t ttsvd_cores_size(const int64_t *dims, int d, int64_t r_max);
+
+/*
+ * ttsvd_decompose_ws -- ttsvd_decompose (Algorithm 2) with caller-owned
+ * device buffers, so the call makes no device allocation and no device free:
+ *
+ *   ws, ws_bytes       device workspace, 256-byte aligned, ws_bytes >=
+ *                      ttsvd_workspace_size(dims, d, r_max, X->dtype).  Its
+ *                      contents on entry do not matter; on return they are
+ *                      undefined.  It must not overlap X or cores.
+ *   cores, cores_doubles  device FP64 buffer of cores_doubles >=
+ *                      ttsvd_cores_size(dims, d, r_max) values; out->cores[j]
+ *                      point into it (core j at the offset of the rank upper
+ *                      bounds of the cores left of it).  It stays owned by the
+ *                      caller: ttsvd_tt_free releases only the host arrays of
+ *                      out, and the cores stay valid until the caller reuses
+ *                      or frees the buffer.
+ *
+ * Everything else (arguments, outputs, synchronisation of X->stream before
+ * returning, errors) is as in ttsvd_decompose; additionally TTSVD_EINVAL for
+ * NULL, short or misaligned buffers.  One pinned host staging buffer per
+ * calling thread is allocated on the thread's first call and reused.  Two
+ * calls that use the same ws at the same time race.
+ */
+int ttsvd_decompose_ws(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r_max,
+                       double tol, void *ws, size_t ws_bytes, double *cores,
+                       size_t cores_doubles, ttsvd_tt *out);
+
+/*
  * Thick-bounds variant (Algorithm 3, Sec. 3.1.3 "Thick-bounds variant").
  *
  * ttsvd_thick_bounds_k -- number k of right-most modes to combine: the
@@ -280,9 +324,14 @@ int ttsvd_server_default_config(ttsvd_server_config *cfg);
 /* Start a server on the calling thread's current device.  Errors: TTSVD_EINVAL. */
 int ttsvd_server_create(const ttsvd_server_config *cfg, ttsvd_server **out);
 /* Queue a decomposition of X (device memory that must stay valid and unchanged
- * until its completion is returned; X->stream is ignored).  Arguments as in
- * ttsvd_decompose; *ticket identifies the request.  Errors: TTSVD_EINVAL,
- * TTSVD_EUNSUPPORTED. */
+ * until its completion is returned).  X->stream is the stream that produced
+ * X (a stream of the server's device, NULL = the legacy default stream): the
+ * call records an event on it, and the request's work starts only after
+ * everything enqueued there before the call, so the producer need not
+ * synchronise before submitting.  The request itself runs on a worker's
+ * stream.  Arguments as in ttsvd_decompose; *ticket identifies the request.
+ * Errors: TTSVD_EINVAL, TTSVD_EUNSUPPORTED, TTSVD_EHIP (the event could not
+ * be recorded on X->stream). */
 int ttsvd_server_submit(ttsvd_server *s, const ttsvd_tensor *X, const int64_t *dims, int d,
                         int64_t r_max, double tol, uint64_t *ticket);
 /* Move up to max finished requests into out (waiting up to wait_ms for the

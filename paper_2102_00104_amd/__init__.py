@@ -33,7 +33,8 @@ EXPORTED = ["ttsvd_tsqr_r", "ttsvd_tsqr_workspace_size", "ttsvd_gemm_reshape",
             "ttsvd_batch_default_config", "ttsvd_decompose_batch", "ttsvd_batch_autotune",
             "ttsvd_server_default_config", "ttsvd_server_create", "ttsvd_server_submit",
             "ttsvd_server_poll", "ttsvd_server_pending", "ttsvd_server_destroy",
-            "ttsvd_server_clock", "ttsvd_thick_bounds_k", "ttsvd_decompose_thick"]
+            "ttsvd_server_clock", "ttsvd_thick_bounds_k", "ttsvd_decompose_thick",
+            "ttsvd_workspace_size", "ttsvd_cores_size", "ttsvd_decompose_ws"]
 
 
 class TTSVDError(RuntimeError):
@@ -141,6 +142,14 @@ def lib() -> ctypes.CDLL:
         L.ttsvd_decompose.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64), ctypes.c_int,
                                       i64, ctypes.c_double, ctypes.POINTER(TTStruct)]
         L.ttsvd_decompose.restype = ctypes.c_int
+        L.ttsvd_workspace_size.argtypes = [ctypes.POINTER(i64), ctypes.c_int, i64, ctypes.c_int]
+        L.ttsvd_workspace_size.restype = ctypes.c_size_t
+        L.ttsvd_cores_size.argtypes = [ctypes.POINTER(i64), ctypes.c_int, i64]
+        L.ttsvd_cores_size.restype = ctypes.c_size_t
+        L.ttsvd_decompose_ws.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64),
+                                         ctypes.c_int, i64, ctypes.c_double, vp, ctypes.c_size_t,
+                                         vp, ctypes.c_size_t, ctypes.POINTER(TTStruct)]
+        L.ttsvd_decompose_ws.restype = ctypes.c_int
         L.ttsvd_thick_bounds_k.argtypes = [ctypes.POINTER(i64), ctypes.c_int, i64, ctypes.c_double, i64,
                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64)]
         L.ttsvd_thick_bounds_k.restype = ctypes.c_int
@@ -324,6 +333,38 @@ def ttsvd_decompose(X, dims: Sequence[int], r_max: int, tol: float, ld_last: int
         lib().ttsvd_tt_free(ctypes.byref(out))
 
 
+def ttsvd_workspace_size(dims: Sequence[int], r_max: int, dtype: int) -> int:
+    arr = (ctypes.c_int64 * max(1, len(dims)))(*[int(n) for n in dims])
+    return int(lib().ttsvd_workspace_size(arr, len(dims), int(r_max), int(dtype)))
+
+
+def ttsvd_cores_size(dims: Sequence[int], r_max: int) -> int:
+    arr = (ctypes.c_int64 * max(1, len(dims)))(*[int(n) for n in dims])
+    return int(lib().ttsvd_cores_size(arr, len(dims), int(r_max)))
+
+
+def ttsvd_decompose_ws(X, dims: Sequence[int], r_max: int, tol: float, ws, cores,
+                       ld_last: int = 0, stream=None, fetch: bool = True) -> TT:
+    """``ttsvd_decompose_ws``: ``ttsvd_decompose`` with the caller's device
+    workspace ``ws`` (a torch tensor of at least ``ttsvd_workspace_size`` bytes)
+    and FP64 core buffer ``cores`` (at least ``ttsvd_cores_size`` values); the
+    call allocates no device memory.  With fetch=False the cores are not copied
+    out (they stay in ``cores``)."""
+    dims = [int(n) for n in dims]
+    d = len(dims)
+    st = _stream(stream)
+    xs = TensorStruct(X.data_ptr(), dtype_code(X), ld_last, st)
+    arr = (ctypes.c_int64 * d)(*dims)
+    out = TTStruct()
+    _check(lib().ttsvd_decompose_ws(ctypes.byref(xs), arr, d, r_max, float(tol), ws.data_ptr(),
+                                    ws.numel() * ws.element_size(), cores.data_ptr(),
+                                    cores.numel() * cores.element_size() // 8, ctypes.byref(out)))
+    try:
+        return _to_tt(out, X.device, st, fetch)
+    finally:
+        lib().ttsvd_tt_free(ctypes.byref(out))
+
+
 def thick_bounds_k(dims: Sequence[int], m_min: int, f1_min: float, r_est: int):
     """``ttsvd_thick_bounds_k``: (k, m) of the thick-bounds variant."""
     dims = [int(n) for n in dims]
@@ -429,8 +470,10 @@ class Server:
         cfg = cfg if cfg is not None else server_default_config()
         _check(lib().ttsvd_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
 
-    def submit(self, X, dims: Sequence[int], r_max: int, tol: float) -> int:
-        xs = TensorStruct(X.data_ptr(), dtype_code(X), 0, None)
+    def submit(self, X, dims: Sequence[int], r_max: int, tol: float, stream=None) -> int:
+        """Queue X; its work starts after what was enqueued on ``stream`` (the
+        producer's stream, default: torch's current stream) before the call."""
+        xs = TensorStruct(X.data_ptr(), dtype_code(X), 0, _stream(stream))
         arr = (ctypes.c_int64 * len(dims))(*[int(n) for n in dims])
         t = ctypes.c_uint64(0)
         _check(lib().ttsvd_server_submit(self._h, ctypes.byref(xs), arr, len(dims), int(r_max),

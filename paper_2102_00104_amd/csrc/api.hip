@@ -111,6 +111,26 @@ Footprint footprint(const int64_t *dims, int d, int dtype, const std::vector<Ste
     return f;
 }
 
+// Offsets (bytes) of the parts of a decomposition's workspace: the two
+// ping-pong work matrices, R, the TSQR tree, the SVD scratch, sigma and the
+// device state, each 256-byte aligned.
+struct WsLayout {
+    size_t w0, w1, r, tq, sv, sg, st, total;
+};
+
+WsLayout ws_layout(const Footprint &f, size_t es) {
+    WsLayout l;
+    l.w0 = 0;
+    l.w1 = l.w0 + align256(f.wbuf[0] * es);
+    l.r = l.w1 + align256(f.wbuf[1] * es);
+    l.tq = l.r + align256(f.rbuf * 8);
+    l.sv = l.tq + align256(f.tsqr_ws);
+    l.sg = l.sv + align256(f.svd_ws);
+    l.st = l.sg + align256(f.sigma * 8);
+    l.total = l.st + align256(sizeof(DecompState));
+    return l;
+}
+
 }  // namespace
 
 // Keep freed stream-ordered allocations in the device's default pool instead
@@ -258,10 +278,7 @@ size_t ttsvd_footprint_bytes(const int64_t *dims, int d, int64_t r_max, int dtyp
     int64_t nbar;
     if (plan_steps(dims, d, r_max, steps, rb, nbar) != TTSVD_OK) return 0;
     Footprint f = footprint(dims, d, dtype, steps, rb);
-    const size_t es = dtype_size(dtype);
-    return align256(f.wbuf[0] * es) + align256(f.wbuf[1] * es) + align256(f.rbuf * 8) +
-           align256(f.tsqr_ws) + align256(f.svd_ws) + align256(f.sigma * 8) +
-           align256(sizeof(DecompState)) + align256(f.cores * 8);
+    return ws_layout(f, dtype_size(dtype)).total + align256(f.cores * 8);
 }
 
 void ttsvd_tt_free(ttsvd_tt *tt) {
@@ -279,8 +296,9 @@ void ttsvd_tt_free(ttsvd_tt *tt) {
     memset(tt, 0, sizeof(*tt));
 }
 
-int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r_max, double tol,
-                    ttsvd_tt *out) {
+static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r_max,
+                          double tol, void *ws_in, size_t ws_bytes, double *cores_in,
+                          size_t cores_doubles, ttsvd_tt *out) {
     clear_error();
     if (!X || !X->data || !dims || !out) return set_error(TTSVD_EINVAL, "decompose: NULL pointer");
     if (d < 1 || d > TTSVD_MAX_D) return set_error(TTSVD_EINVAL, "decompose: d = %d", d);
@@ -300,45 +318,54 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r
             return set_error(TTSVD_EUNSUPPORTED, "decompose: step with %lld > 1024 columns",
                              (long long)steps[i].m);
 
-    memset(out, 0, sizeof(*out));
-    const hipStream_t s = X->stream;
-    rc = keep_pool_memory(s);
-    if (rc != TTSVD_OK) return rc;
     const int dt = X->dtype;
     const size_t es = dtype_size(dt);
     Footprint f = footprint(dims, d, dt, steps, rb);
+    const WsLayout lay = ws_layout(f, es);
+    if (ws_in && ws_bytes < lay.total)
+        return set_error(TTSVD_EINVAL, "decompose: workspace %zu < %zu bytes", ws_bytes, lay.total);
+    if (ws_in && ((uintptr_t)ws_in & 255))
+        return set_error(TTSVD_EINVAL, "decompose: workspace not 256-byte aligned");
+    if (cores_in && cores_doubles < f.cores)
+        return set_error(TTSVD_EINVAL, "decompose: core buffer %zu < %zu doubles", cores_doubles,
+                         f.cores);
+
+    memset(out, 0, sizeof(*out));
+    const hipStream_t s = X->stream;
+    if (!ws_in) {
+        rc = keep_pool_memory(s);
+        if (rc != TTSVD_OK) return rc;
+    }
 
     TTPriv *priv = new TTPriv();
     out->priv = priv;
     out->d = d;
     for (int i = 0; i < d; ++i) out->dims[i] = dims[i];
 
-    if (hipMalloc(&priv->cores_dev, std::max<size_t>(f.cores, 1) * 8) != hipSuccess) {
-        ttsvd_tt_free(out);
-        return set_error(TTSVD_ENOMEM, "decompose: cores (%zu doubles)", f.cores);
+    double *cores_base = cores_in;
+    if (!cores_base) {
+        if (hipMalloc(&priv->cores_dev, std::max<size_t>(f.cores, 1) * 8) != hipSuccess) {
+            ttsvd_tt_free(out);
+            return set_error(TTSVD_ENOMEM, "decompose: cores (%zu doubles)", f.cores);
+        }
+        cores_base = priv->cores_dev;
     }
-    for (int i = 0; i < d; ++i) out->cores[i] = priv->cores_dev + f.core_off[i];
+    for (int i = 0; i < d; ++i) out->cores[i] = cores_base + f.core_off[i];
 
-    // One stream-ordered workspace allocation for everything temporary.
-    const size_t o_w0 = 0;
-    const size_t o_w1 = o_w0 + align256(f.wbuf[0] * es);
-    const size_t o_r = o_w1 + align256(f.wbuf[1] * es);
-    const size_t o_tq = o_r + align256(f.rbuf * 8);
-    const size_t o_sv = o_tq + align256(f.tsqr_ws);
-    const size_t o_sg = o_sv + align256(f.svd_ws);
-    const size_t o_st = o_sg + align256(f.sigma * 8);
-    const size_t total = o_st + align256(sizeof(DecompState));
-    char *ws = nullptr;
-    if (hipMallocAsync((void **)&ws, total, s) != hipSuccess) {
+    // One workspace for everything temporary: the caller's, or one
+    // stream-ordered allocation released before returning.
+    char *ws = (char *)ws_in;
+    const bool own_ws = (ws == nullptr);
+    if (own_ws && hipMallocAsync((void **)&ws, lay.total, s) != hipSuccess) {
         ttsvd_tt_free(out);
-        return set_error(TTSVD_ENOMEM, "decompose: workspace of %zu bytes", total);
+        return set_error(TTSVD_ENOMEM, "decompose: workspace of %zu bytes", lay.total);
     }
-    void *wbuf[2] = {ws + o_w0, ws + o_w1};
-    double *Rbuf = (double *)(ws + o_r);
-    void *tq = ws + o_tq;
-    void *sv = ws + o_sv;
-    double *sig_dev = (double *)(ws + o_sg);
-    DecompState *state = (DecompState *)(ws + o_st);
+    void *wbuf[2] = {ws + lay.w0, ws + lay.w1};
+    double *Rbuf = (double *)(ws + lay.r);
+    void *tq = ws + lay.tq;
+    void *sv = ws + lay.sv;
+    double *sig_dev = (double *)(ws + lay.sg);
+    DecompState *state = (DecompState *)(ws + lay.st);
     DecompState hstate;
     memset(&hstate, 0, sizeof(hstate));
     hstate.one = 1.0;
@@ -347,7 +374,8 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r
     do {                                      \
         int rc_ = (expr);                     \
         if (rc_ != TTSVD_OK) {                \
-            (void)hipFreeAsync(ws, s);        \
+            if (own_ws)                       \
+                (void)hipFreeAsync(ws, s);    \
             (void)hipStreamSynchronize(s);    \
             ttsvd_tt_free(out);               \
             return rc_;                       \
@@ -420,7 +448,7 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r
         TTSVD_STEP_HIP(hipMemcpyAsync(stage + align256(sizeof(hstate)), sig_dev, f.sigma * 8,
                                       hipMemcpyDeviceToHost, s));
     TTSVD_STEP_HIP(hipStreamSynchronize(s));
-    TTSVD_STEP_HIP(hipFreeAsync(ws, s));
+    if (own_ws) TTSVD_STEP_HIP(hipFreeAsync(ws, s));
     memcpy(&hstate, stage, sizeof(hstate));
     std::vector<double> sig_host(std::max<size_t>(f.sigma, 1));
     if (f.sigma) memcpy(sig_host.data(), stage + align256(sizeof(hstate)), f.sigma * 8);
@@ -480,6 +508,37 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r
     return TTSVD_OK;
 #undef TTSVD_STEP_TRY
 #undef TTSVD_STEP_HIP
+}
+
+size_t ttsvd_workspace_size(const int64_t *dims, int d, int64_t r_max, int dtype) {
+    if (!dims || d < 1 || d > TTSVD_MAX_D || r_max < 1 || !valid_dtype(dtype)) return 0;
+    std::vector<StepShape> steps;
+    std::vector<int64_t> rb;
+    int64_t nbar;
+    if (plan_steps(dims, d, r_max, steps, rb, nbar) != TTSVD_OK) return 0;
+    return ws_layout(footprint(dims, d, dtype, steps, rb), dtype_size(dtype)).total;
+}
+
+size_t ttsvd_cores_size(const int64_t *dims, int d, int64_t r_max) {
+    if (!dims || d < 1 || d > TTSVD_MAX_D || r_max < 1) return 0;
+    std::vector<StepShape> steps;
+    std::vector<int64_t> rb;
+    int64_t nbar;
+    if (plan_steps(dims, d, r_max, steps, rb, nbar) != TTSVD_OK) return 0;
+    return footprint(dims, d, TTSVD_F64, steps, rb).cores;
+}
+
+int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r_max, double tol,
+                    ttsvd_tt *out) {
+    return decompose_impl(X, dims, d, r_max, tol, nullptr, 0, nullptr, 0, out);
+}
+
+int ttsvd_decompose_ws(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r_max,
+                       double tol, void *ws, size_t ws_bytes, double *cores,
+                       size_t cores_doubles, ttsvd_tt *out) {
+    clear_error();
+    if (!ws || !cores) return set_error(TTSVD_EINVAL, "decompose_ws: NULL workspace or cores");
+    return decompose_impl(X, dims, d, r_max, tol, ws, ws_bytes, cores, cores_doubles, out);
 }
 
 }  // extern "C"

@@ -43,6 +43,7 @@ struct Request {
     size_t footprint;
     bool small;
     double t_submit;
+    hipEvent_t ready;  // recorded on the producer's stream at submission
 };
 
 }  // namespace
@@ -118,6 +119,11 @@ void worker_main(ttsvd_server *S) {
             }
             S->in_use += claimed;
         }
+        // The work of each request starts after what its producer enqueued
+        // before submitting it (the tensor's contents).
+        bool waited = have_stream;
+        for (const Request &q : take)
+            if (waited && hipStreamWaitEvent(st, q.ready, 0) != hipSuccess) waited = false;
         const double t_start = now_s();
         std::vector<ttsvd_completion> comp(take.size());
         for (size_t i = 0; i < take.size(); ++i) {
@@ -128,8 +134,11 @@ void worker_main(ttsvd_server *S) {
             comp[i].batch_size = (int)take.size();
             comp[i].batched = !(take.size() == 1 && !(take[0].small && S->cfg.max_batch > 1));
         }
-        if (!have_stream) {
-            for (auto &c : comp) c.status = TTSVD_EHIP;
+        if (!waited) {
+            for (auto &c : comp) {
+                c.status = TTSVD_EHIP;
+                snprintf(c.message, sizeof(c.message), "server: worker stream or event wait failed");
+            }
         } else if (take.size() == 1 && !(take[0].small && S->cfg.max_batch > 1)) {
             ttsvd_tensor X = take[0].X;
             X.stream = st;
@@ -164,6 +173,9 @@ void worker_main(ttsvd_server *S) {
             }
         }
         const double t_done = now_s();
+        // the decompositions synchronised st, so the waits on these events are done
+        if (have_stream) (void)hipStreamSynchronize(st);
+        for (const Request &q : take) (void)hipEventDestroy(q.ready);
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->in_use -= claimed;
@@ -229,9 +241,19 @@ int ttsvd_server_submit(ttsvd_server *S, const ttsvd_tensor *X, const int64_t *d
     if (r.footprint == 0) return set_error(TTSVD_EINVAL, "submit: invalid problem");
     r.small = is_small(r.dims, r_max, S->cfg.batch_max_elems) && X->ld_last == 0;
     r.t_submit = now_s();
+    r.ready = nullptr;
+    if (hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess)
+        return set_error(TTSVD_EHIP, "submit: hipEventCreateWithFlags");
+    if (hipEventRecord(r.ready, X->stream) != hipSuccess) {
+        (void)hipEventDestroy(r.ready);
+        return set_error(TTSVD_EHIP, "submit: hipEventRecord on the producer's stream");
+    }
     {
         std::lock_guard<std::mutex> lk(S->mu);
-        if (S->stop) return set_error(TTSVD_EINVAL, "submit: server is stopping");
+        if (S->stop) {
+            (void)hipEventDestroy(r.ready);
+            return set_error(TTSVD_EINVAL, "submit: server is stopping");
+        }
         r.ticket = S->next_ticket++;
         *ticket = r.ticket;
         S->queue.push_back(std::move(r));

@@ -43,6 +43,18 @@ def test_host_only_entry_points():
     # two ping-pong work matrices of the size of X dominate (f = 1 steps)
     assert 2 * 8 * 2 ** 28 <= fp <= 3 * 8 * 2 ** 28
     assert tt.ttsvd_footprint_bytes([2] * 28, 0, tt.TTSVD_F64) == 0
+    # caller-buffer sizes: cores at the no-tolerance ranks, and the footprint
+    # is the workspace plus the (256-byte aligned) cores
+    from paper_2102_00104_amd import model
+    for dims, r_max in (([2] * 28, 32), ([16] * 7, 32), ([3, 5, 7, 9], 4), ([9], 3)):
+        rk = model.no_tol_ranks(dims, r_max)
+        nc = sum(rk[j] * dims[j] * rk[j + 1] for j in range(len(dims)))
+        assert tt.ttsvd_cores_size(dims, r_max) == nc
+        ws = tt.ttsvd_workspace_size(dims, r_max, tt.TTSVD_F64)
+        assert ws > 0 and ws % 256 == 0
+        assert tt.ttsvd_footprint_bytes(dims, r_max, tt.TTSVD_F64) == ws + (nc * 8 + 255) // 256 * 256
+    assert tt.ttsvd_workspace_size([2] * 28, 32, 7) == 0
+    assert tt.ttsvd_cores_size([2, 0, 2], 4) == 0
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

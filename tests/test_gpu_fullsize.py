@@ -1,14 +1,17 @@
-"""GPU checks at the benchmark's full size: the 2^28-element FP64 U[0,1)
+"""GPU parity at the benchmark's full size: the 2^28-element FP64 U[0,1)
 tensor (seed 0) decomposed as d = 28, n_i = 2 and d = 7, n_i = 16 with
-r_max = 32 and no tolerance, in the launch configuration bench.py times.
+r_max = 32 and no tolerance, through the caller-workspace entry point that
+bench.py times (ttsvd_decompose_ws, the same kernels and launch shapes as
+ttsvd_decompose).
 
-The whole result cannot be compared with the oracle at this size, so the
-test checks what holds at any size -- the ranks of the no-tolerance rule,
-orthonormal rows of every core right of the first, and the norm identity
-||T^(1)||_F^2 + sum of discarded sigma^2 = ||X||_F^2 (the cores to the right
-are orthonormal) -- and one sampled output the oracle computes directly:
-the singular values of the first step's unfolding (Householder QR and Jacobi
-SVD of the n_1...n_{d-1} x n_d matrix on the host).
+The oracle (Householder QR + Jacobi SVD of every unfolding, Algorithm 2 in
+the paper's order) runs on the same values on the host, so every step is
+compared: identical ranks, every kept singular value to 1e-10 relative and
+all of them to 1e-10 sigma_1 of their step, and the relative reconstruction
+errors ||X - X~||_F / ||X||_F of the two results equal to 1e-12 (both
+contracted on the host in FP64).  Properties that hold at any size are
+checked too: orthonormal rows of every core right of the first, and the norm
+identity ||T^(1)||_F^2 + sum of discarded sigma^2 = ||X||_F^2.
 """
 import numpy as np
 import pytest
@@ -26,6 +29,7 @@ import paper_2102_00104_amd as tt  # noqa: E402
 
 DEV = torch.device("cuda:0")
 N = 1 << 28
+R_MAX = 32
 
 
 @pytest.fixture(scope="module")
@@ -37,15 +41,34 @@ def full_tensor():
     torch.cuda.empty_cache()
 
 
+def decompose_like_bench(Xd, dims):
+    ws = torch.empty(tt.ttsvd_workspace_size(dims, R_MAX, tt.TTSVD_F64), dtype=torch.uint8,
+                     device=DEV)
+    cores = torch.empty(tt.ttsvd_cores_size(dims, R_MAX), dtype=torch.float64, device=DEV)
+    g = tt.ttsvd_decompose_ws(Xd, dims, R_MAX, 0.0, ws, cores)
+    del ws, cores
+    return g
+
+
+@pytest.mark.timeout(1200)
 @pytest.mark.parametrize("dims", [[2] * 28, [16] * 7], ids=["d28n2", "d7n16"])
-def test_full_size_properties_and_first_step(full_tensor, dims):
+def test_full_size_every_step_matches_oracle(full_tensor, dims):
     Xh, Xd = full_tensor
-    print("[fullsize] %s" % (dims,), flush=True)
-    r_max = 32
-    g = tt.ttsvd_decompose(Xd, dims, r_max, 0.0)
     d = len(dims)
-    assert g.ranks == model.no_tol_ranks(dims, r_max)
-    # cores 2..d: orthonormal rows of (r_{j-1}) x (n_j r_j)
+    print("[fullsize] %s: GPU" % (dims,), flush=True)
+    g = decompose_like_bench(Xd, dims)
+    assert g.ranks == model.no_tol_ranks(dims, R_MAX)
+    print("[fullsize] %s: oracle" % (dims,), flush=True)
+    o = oracle.ttsvd(Xh, dims, R_MAX, 0.0)
+    assert g.ranks == o.ranks
+    for j in range(1, d):
+        sg = np.asarray(g.sigma[j])
+        so = o.sigma[j]
+        assert len(sg) == len(so), j
+        r = o.ranks[j]
+        assert np.all(np.abs(sg[:r] - so[:r]) <= 1e-10 * so[:r]), j
+        assert np.max(np.abs(sg - so)) <= 1e-10 * so[0], j
+    # cores 2..d: orthonormal rows of the (r_{j-1}) x (n_j r_j) unfolding
     for j in range(1, d):
         r, n, rn = g.ranks[j], dims[j], g.ranks[j + 1]
         M = g.cores[j].reshape(n * rn, r).T  # Fortran (r, n, rn) -> r x (n rn)
@@ -57,10 +80,10 @@ def test_full_size_properties_and_first_step(full_tensor, dims):
     disc = sum(g.discarded2[1:])
     assert abs(c1 + disc - nx2) <= 1e-10 * nx2
     assert abs(g.err_bound ** 2 - disc) <= 1e-12 * nx2
-    # first step: singular values of the (N / n_d) x n_d unfolding
-    W = Xh.reshape(N // dims[-1], dims[-1], order="F")
-    sig_o, _ = oracle.jacobi_svd(oracle.qr_r(W))
-    K = dims[-1]
-    sg = np.asarray(g.sigma[d - 1])
-    assert len(sg) == K
-    assert np.max(np.abs(sg - sig_o[:K])) <= 1e-10 * sig_o[0]
+    # relative reconstruction errors of both results (host contraction, FP64)
+    print("[fullsize] %s: reconstructions" % (dims,), flush=True)
+    cores = [tt.core_array(c, (g.ranks[j], dims[j], g.ranks[j + 1])) for j, c in enumerate(g.cores)]
+    eg = oracle.rel_error(Xh, oracle.tt_full(cores))
+    eo = oracle.rel_error(Xh, oracle.tt_full(o.cores))
+    print("[fullsize] %s: rel. error GPU %.15f oracle %.15f" % (dims, eg, eo), flush=True)
+    assert abs(eg - eo) <= 1e-12, (eg, eo)
