@@ -82,6 +82,32 @@ int ttsvd_tsqr_r(const void *W, int dtype, int64_t rows, int64_t cols,
 size_t ttsvd_tsqr_workspace_size(int dtype, int64_t rows, int64_t cols);
 
 /*
+ * ttsvd_tsqr_r_noalloc -- ttsvd_tsqr_r without any device allocation.
+ *
+ * For callers that cannot allocate device memory during the call (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and result as ttsvd_tsqr_r, minus the
+ * workspace: the triangular factors of the reduction tree live in one fixed
+ * device array of TTSVD_NOALLOC_SCRATCH_BYTES bytes inside the library (one
+ * copy per GPU, held until the process ends; its address is looked up once
+ * per device).  The call makes no hipMalloc, hipFree or other allocating
+ * call; W is read only and R is written as by ttsvd_tsqr_r.
+ *
+ * All calls on one GPU share that array, whose contents persist from call
+ * to call (nothing in it needs to start at zero): calls that overlap on one
+ * GPU (different streams, or different host threads without ordering) race
+ * on it and must be serialised by the caller.  Calls on different GPUs do
+ * not interact.
+ *
+ * Errors: as ttsvd_tsqr_r, plus TTSVD_EINVAL when the shape needs more
+ * than TTSVD_NOALLOC_SCRATCH_BYTES of tree storage
+ * (ttsvd_tsqr_workspace_size(dtype, rows, cols) > the limit).
+ */
+#define TTSVD_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int ttsvd_tsqr_r_noalloc(const void *W, int dtype, int64_t rows, int64_t cols,
+                         int64_t ld, double *R, int64_t ldr, hipStream_t stream);
+
+/*
  * ttsvd_gemm_reshape -- fused tall-skinny matrix product and reshape.
  *
  * Defined in Sec. 4.1.2 (TSMM): Y <- reshape(W V, (rows/n_next, n_next*k)),

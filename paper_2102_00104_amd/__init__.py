@@ -34,7 +34,8 @@ EXPORTED = ["ttsvd_tsqr_r", "ttsvd_tsqr_workspace_size", "ttsvd_gemm_reshape",
             "ttsvd_server_default_config", "ttsvd_server_create", "ttsvd_server_submit",
             "ttsvd_server_poll", "ttsvd_server_pending", "ttsvd_server_destroy",
             "ttsvd_server_clock", "ttsvd_thick_bounds_k", "ttsvd_decompose_thick",
-            "ttsvd_workspace_size", "ttsvd_cores_size", "ttsvd_decompose_ws"]
+            "ttsvd_workspace_size", "ttsvd_cores_size", "ttsvd_decompose_ws",
+            "ttsvd_tsqr_r_noalloc"]
 
 
 class TTSVDError(RuntimeError):
@@ -137,6 +138,8 @@ def lib() -> ctypes.CDLL:
         L.ttsvd_tsqr_r.restype = ctypes.c_int
         L.ttsvd_tsqr_workspace_size.argtypes = [ctypes.c_int, i64, i64]
         L.ttsvd_tsqr_workspace_size.restype = ctypes.c_size_t
+        L.ttsvd_tsqr_r_noalloc.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, vp]
+        L.ttsvd_tsqr_r_noalloc.restype = ctypes.c_int
         L.ttsvd_gemm_reshape.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64, i64, vp, i64, vp]
         L.ttsvd_gemm_reshape.restype = ctypes.c_int
         L.ttsvd_decompose.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64), ctypes.c_int,
@@ -248,6 +251,17 @@ def ttsvd_tsqr_r(W, dtype: int, rows: int, cols: int, ld: int, R, ldr: int,
 
 def ttsvd_tsqr_workspace_size(dtype: int, rows: int, cols: int) -> int:
     return int(lib().ttsvd_tsqr_workspace_size(dtype, rows, cols))
+
+
+def ttsvd_tsqr_r_noalloc(W, dtype: int, rows: int, cols: int, ld: int, R, ldr: int,
+                         stream=None) -> None:
+    """``ttsvd_tsqr_r_noalloc``: ``ttsvd_tsqr_r`` with the library's fixed
+    device scratch instead of a workspace (no device allocation)."""
+    _check(lib().ttsvd_tsqr_r_noalloc(W.data_ptr(), dtype, rows, cols, ld, R.data_ptr(), ldr,
+                                      _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 
 def ttsvd_gemm_reshape(W, dtype: int, rows: int, cols: int, ld: int, V, ldv: int, k: int,
