@@ -438,23 +438,146 @@ def serving(tt, duration):
             "server": fast, "sequential": seq}
 
 
-def cpu_baseline(d_sample, r_max):
-    """The CPU FP64 oracle on a bounded sample of the same workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of this process (the oracle's C code)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
+def cpu_baseline(d_sample, r_max, d_single=25):
+    """The CPU FP64 oracle on bounded samples of the same workload: all host
+    cores on a 2^d_sample tensor, and one thread on a 2^d_single tensor."""
     import numpy as np
 
     import oracle
     from paper_2102_00104_amd import model
-    dims = [2] * d_sample
-    X = np.random.default_rng(0).random(2 ** d_sample)
-    t0 = time.perf_counter()
-    o = oracle.ttsvd(X, dims, r_max, 0.0)
-    dt = time.perf_counter() - t0
-    b = model.algorithmic_bytes(dims, o.ranks, 8)
+
+    def run(d):
+        dims = [2] * d
+        X = np.random.default_rng(0).random(2 ** d)
+        t0 = time.perf_counter()
+        o = oracle.ttsvd(X, dims, r_max, 0.0)
+        dt = time.perf_counter() - t0
+        return model.algorithmic_bytes(dims, o.ranks, 8) / dt / 1e9, dt
+
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-    return {"value": round(b / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+    gbs, dt = run(d_sample)
+    single = None
+    if _omp_threads(1):
+        try:
+            g1, dt1 = run(d_single)
+            single = {"value": round(g1, 4), "unit": "GB/s", "cores": 1,
+                      "sample": "2^%d-element tensor, d=%d, n_i=2, r_max=%d; %.2f s" % (
+                          d_single, d_single, r_max, dt1)}
+        finally:
+            _omp_threads(threads)
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": "2^%d-element U[0,1) FP64 tensor, d=%d, n_i=2, r_max=%d, no tol "
                       "(1/%d of the workload); %.2f s" % (d_sample, d_sample, r_max,
-                                                          2 ** (28 - d_sample), dt)}
+                                                          2 ** (28 - d_sample), dt),
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "single_thread": single}
+
+
+def machine(tt):
+    """Measured roofline denominators (the analog of the paper's Table 1):
+    load, store, copy and triad HBM bandwidth over 3 GiB, and the FP64 FMA
+    rate, from the library's micro-benchmark kernels."""
+    import torch
+    buf = torch.zeros(3 * 2 ** 27, dtype=torch.float64, device="cuda:0")
+    res = {}
+    for kind, name in ((tt.MB_LOAD, "load"), (tt.MB_STORE, "store"), (tt.MB_COPY, "copy"),
+                       (tt.MB_TRIAD, "triad")):
+        ms, by = tt.ttsvd_machine_bench(kind, buf, 20)
+        res[name + "_GBs"] = round(by / ms / 1e6, 1)
+    ms, fl = tt.ttsvd_machine_bench(tt.MB_FMA, buf, 10)
+    res["fp64_fma_TFs"] = round(fl / ms / 1e9, 2)
+    del buf
+    torch.cuda.empty_cache()
+    return res
+
+
+def family_split(stats, ndec):
+    """Milliseconds per decomposition spent in each building block (the
+    analog of the paper's per-function timings): TSQR, small SVD, TSMM."""
+    fam = {"tsqr": 0.0, "svd": 0.0, "tsmm": 0.0, "other": 0.0}
+    for s in stats:
+        n = s["name"]
+        key = ("tsqr" if n.startswith("tsqr") else "svd" if n.startswith("svd")
+               else "tsmm" if n.startswith("tsmm") else "other")
+        fam[key] += s["total_ms"]
+    return {k + "_ms": round(v / ndec, 3) for k, v in fam.items()}
+
+
+def small_latency(tt, steps, warmup):
+    """The d = 12 exact-TT workload (4096 values): latency of one
+    decomposition in microseconds."""
+    import torch
+
+    from paper_2102_00104_amd import synth
+    dims, X, r_max, tol = synth.small_exact_tt_workload()
+    Xd = torch.from_numpy(X).to("cuda:0")
+    n = max(steps, 20)
+    sec, res, med = time_decompose(tt, Xd, dims, r_max, tol, n, max(warmup, 3))
+    return {"workload": "d=12, n_i=2 exact TT (ranks 4, Gaussian cores) + 1e-8 noise, "
+                        "r_max=8, tol=1e-10, FP64", "median_us": round(med * 1e6, 1),
+            "mean_us": round(sec * 1e6, 1), "calls": n, "ranks": res.ranks}
+
+
+def sweeps(tt):
+    """GB/s and TFLOP/s of ttsvd_tsqr_r and ttsvd_gemm_reshape against the
+    column count m on 1 GiB FP64 inputs (rows = 2^27 / m; the product has
+    k = max(1, m / 2) columns and n_next = 2), the analog of the paper's
+    roofline plots of the two building blocks (median of 5 calls)."""
+    import torch
+    out = {"tsqr_r": [], "gemm_reshape": []}
+    dev = torch.device("cuda:0")
+    for m in (1, 2, 4, 8, 16, 32, 50, 64, 100, 128):
+        rows = (2 ** 27 // m) // 2 * 2
+        W = torch.rand(rows * m, dtype=torch.float64, device=dev)
+        R = torch.empty(m * m, dtype=torch.float64, device=dev)
+        need = tt.ttsvd_tsqr_workspace_size(tt.TTSVD_F64, rows, m)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        k = max(1, m // 2)
+        V = torch.rand(m * k, dtype=torch.float64, device=dev)
+        Y = torch.empty(rows * k, dtype=torch.float64, device=dev)
+
+        def med(fn):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            return sorted(ts)[2]
+        t = med(lambda: tt.ttsvd_tsqr_r(W, tt.TTSVD_F64, rows, m, rows, R, m, ws, need))
+        out["tsqr_r"].append({"m": m, "rows": rows, "ms": round(t * 1e3, 3),
+                              "GBs": round(8.0 * rows * m / t / 1e9, 1),
+                              "TFs": round(2.0 * rows * m * m / t / 1e12, 2)})
+        t = med(lambda: tt.ttsvd_gemm_reshape(W, tt.TTSVD_F64, rows, m, rows, V, m, k, 2, Y,
+                                              rows // 2))
+        out["gemm_reshape"].append({"m": m, "k": k, "rows": rows, "ms": round(t * 1e3, 3),
+                                    "GBs": round(8.0 * rows * (m + k) / t / 1e9, 1),
+                                    "TFs": round(2.0 * rows * m * k / t / 1e12, 2)})
+        del W, R, ws, V, Y
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -471,6 +594,9 @@ def main():
     ap.add_argument("--no-thick", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--no-machine", action="store_true")
+    ap.add_argument("--no-sweeps", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -503,7 +629,8 @@ def main():
         assert res.ranks == ranks, (res.ranks, ranks)
         log("%s: %.3f ms/step (median %.3f ms), %.1f GB/s" % (wname, sec * 1e3, med * 1e3,
                                                              abytes / sec / 1e9))
-        stats = kernel_profile(tt, X, dims, args.r_max, 0.0, max(1, min(args.steps, 3)))
+        nprof = max(1, min(args.steps, 3))
+        stats = kernel_profile(tt, X, dims, args.r_max, 0.0, nprof)
         for s in sorted(stats, key=lambda s: -s["total_ms"]):
             log("  %-40s n=%4d  %9.3f ms  %8.1f GB/s  %6.2f TF/s" % (
                 s["name"], s["launches"], s["total_ms"],
@@ -512,7 +639,8 @@ def main():
         results.append(dict(workload=wname, dims=dims, ranks=ranks, ms_per_step=sec * 1e3,
                             median_ms=med * 1e3, value_median=abytes / med / 1e9,
                             value=abytes / sec / 1e9, bytes=abytes, flops=aflops,
-                            roofline=roofline_of(stats, wname), kernels=stats, sec=sec, res=res))
+                            roofline=roofline_of(stats, wname), kernels=stats, sec=sec, res=res,
+                            split=family_split(stats, nprof)))
 
     if args.copy_calibration:
         # a plain copy of known size: reads 2^27 doubles, writes 2^27 doubles
@@ -543,12 +671,24 @@ def main():
                    "algorithmic_bytes": head["bytes"], "flops": head["flops"],
                    "hbm_roofline_frac": round(head["value"] / HBM_PEAK_GBS, 4)},
         "roofline": head["roofline"],
+        "time_split": head["split"],
         "others": [{"workload": r["workload"], "value": round(r["value"], 2), "unit": "GB/s",
                     "ms_per_step": round(r["ms_per_step"], 3),
                     "median_ms_per_step": round(r["median_ms"], 3),
                     "hbm_roofline_frac": round(r["value"] / HBM_PEAK_GBS, 4),
-                    "roofline": r["roofline"]} for r in results[1:]],
+                    "roofline": r["roofline"], "time_split": r["split"]} for r in results[1:]],
     }
+    if not args.no_machine:
+        mach = machine(tt)
+        log("machine: %s" % mach)
+        mach["headline_frac_of_measured_load"] = round(head["value"] / mach["load_GBs"], 4)
+        line["machine"] = mach
+    if not args.no_small:
+        line["small_latency"] = small_latency(tt, args.steps, args.warmup)
+        log("small workload: %s" % line["small_latency"])
+    if not args.no_sweeps:
+        line["sweeps"] = sweeps(tt)
+        log("sweeps: %s" % line["sweeps"])
     if not args.no_precision:
         line["precision_forms"] = precision_forms(tt, X, head["dims"], args.r_max, args.steps,
                                                   args.warmup, head["sec"], head["res"])

@@ -66,8 +66,9 @@ enum {
  *          If rows < cols only the first rows rows of R are significant;
  *          rows rows..cols-1 are set to 0.  Row signs are unspecified.
  *   ws     device workspace of ws_bytes bytes (see ttsvd_tsqr_workspace_size),
- *          or NULL: the library then allocates it stream-ordered on `stream`
- *          (hipMallocAsync) and frees it the same way after the launches.
+ *          or NULL: the library then takes a block of its device buffer
+ *          cache and returns it to the cache from a host callback enqueued on
+ *          `stream` after the launches (the call stays asynchronous).
  *   stream HIP stream; the call is asynchronous with respect to the host.
  *
  * Errors: TTSVD_EINVAL for rows < 1, cols < 1, ld < rows, ldr < cols, NULL
@@ -270,7 +271,9 @@ int ttsvd_decompose_thick(const ttsvd_tensor *X, const int64_t *dims, int d,
  */
 typedef struct ttsvd_batch_config {
     int grid;        /* workgroups of the persistent launch; 0 = all co-resident ones */
-    int tile_set;    /* register tiling of the TSQR bodies (0)                      */
+    int tile_set;    /* register tiling of the TSQR bodies: 0 (rows per lane 8 for
+                        m <= 8; 16, 8, 4, 2 for the 16-, 32-, 64- and 128-column
+                        buckets) for every dtype; 1 (half of those) for FP32 */
     int min_tiles;   /* a TSQR slice spans at least this many row tiles (>= 1)      */
     int max_slices;  /* TSQR slices per tensor and tree level at most (>= 1)        */
 } ttsvd_batch_config;
@@ -307,8 +310,10 @@ int ttsvd_decompose_batch(int count, const ttsvd_tensor *X, const int *d,
 
 /*
  * ttsvd_batch_autotune -- time the batch under each candidate configuration
- * (TSQR slice sizes and counts, tile sets), return the fastest in *best and
- * its time in *best_ms (may be NULL), and remember it for later
+ * (TSQR slice sizes and counts, tile sets built for the dtype), return the
+ * fastest in *best and its time in *best_ms (may be NULL): the host wall
+ * time of one call plus the release of its results, the span a caller sees.
+ * The choice is remembered for later
  * ttsvd_decompose_batch calls with cfg = NULL on the same batch (same count,
  * dtype, dims, r_max, tol and strides).  The decompositions it runs are
  * discarded.  Errors as ttsvd_decompose_batch.
@@ -371,7 +376,9 @@ void ttsvd_server_destroy(ttsvd_server *s);
 double ttsvd_server_clock(void);
 
 /* Release the buffers of a ttsvd_tt filled by ttsvd_decompose or
- * ttsvd_decompose_batch (NULL-safe). */
+ * ttsvd_decompose_batch (NULL-safe).  Library-owned cores go back to the
+ * library's device buffer cache after the device is synchronised (as hipFree
+ * would); they are not returned to the driver, so repeated calls reuse them. */
 void ttsvd_tt_free(ttsvd_tt *tt);
 
 /* Device bytes ttsvd_decompose allocates for this problem (work matrices,
@@ -412,6 +419,33 @@ void ttsvd_profile_reset(void);
  * to max_stats entries to stats and the number of distinct kernels to
  * *n_stats.  Errors: TTSVD_EINVAL (NULL pointers), TTSVD_EHIP. */
 int ttsvd_profile_read(ttsvd_kernel_stat *stats, int max_stats, int *n_stats);
+
+/*
+ * Machine micro-benchmarks: the measured denominators of the roofline report
+ * (the analog of the machine characterisation of Sec. 5, Table 1: load,
+ * store, copy and triad memory bandwidth and the FP64 FMA rate).  Not part of
+ * the method.
+ *
+ *   kind   TTSVD_MB_LOAD (sum of a[i]), TTSVD_MB_STORE (a[i] = 0),
+ *          TTSVD_MB_COPY (b[i] = a[i]), TTSVD_MB_TRIAD (a[i] = b[i] + s c[i]),
+ *          TTSVD_MB_FMA (independent FP64 FMA chains, no memory traffic).
+ *   buf    device buffer of `bytes` bytes, split into 1, 2 or 3 equal arrays
+ *          (load/store, copy, triad); zero-filled by the caller for LOAD.
+ *          For FMA it must hold one double (never written in practice).
+ *   reps   timed launches after one untimed warm-up, on `stream`.
+ *   out    host: out[0] = milliseconds per launch (HIP events),
+ *          out[1] = bytes moved (or flops for FMA) per launch.
+ * Synchronises the stream.  Errors: TTSVD_EINVAL, TTSVD_EHIP.
+ */
+enum {
+    TTSVD_MB_LOAD = 0,
+    TTSVD_MB_STORE = 1,
+    TTSVD_MB_COPY = 2,
+    TTSVD_MB_TRIAD = 3,
+    TTSVD_MB_FMA = 4
+};
+int ttsvd_machine_bench(int kind, void *buf, size_t bytes, int reps, hipStream_t stream,
+                        double *out);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,7 @@ EXPORTED = ["ttsvd_tsqr_r", "ttsvd_tsqr_workspace_size", "ttsvd_gemm_reshape",
             "ttsvd_server_poll", "ttsvd_server_pending", "ttsvd_server_destroy",
             "ttsvd_server_clock", "ttsvd_thick_bounds_k", "ttsvd_decompose_thick",
             "ttsvd_workspace_size", "ttsvd_cores_size", "ttsvd_decompose_ws",
-            "ttsvd_tsqr_r_noalloc"]
+            "ttsvd_tsqr_r_noalloc", "ttsvd_machine_bench"]
 
 
 class TTSVDError(RuntimeError):
@@ -140,6 +140,8 @@ def lib() -> ctypes.CDLL:
         L.ttsvd_tsqr_workspace_size.restype = ctypes.c_size_t
         L.ttsvd_tsqr_r_noalloc.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, vp]
         L.ttsvd_tsqr_r_noalloc.restype = ctypes.c_int
+        L.ttsvd_machine_bench.argtypes = [ctypes.c_int, vp, ctypes.c_size_t, ctypes.c_int, vp, dp]
+        L.ttsvd_machine_bench.restype = ctypes.c_int
         L.ttsvd_gemm_reshape.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64, i64, vp, i64, vp]
         L.ttsvd_gemm_reshape.restype = ctypes.c_int
         L.ttsvd_decompose.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64), ctypes.c_int,
@@ -262,6 +264,16 @@ def ttsvd_tsqr_r_noalloc(W, dtype: int, rows: int, cols: int, ld: int, R, ldr: i
 
 
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+MB_LOAD, MB_STORE, MB_COPY, MB_TRIAD, MB_FMA = 0, 1, 2, 3, 4
+
+
+def ttsvd_machine_bench(kind: int, buf, reps: int = 10, stream=None):
+    """``ttsvd_machine_bench``: (ms per launch, bytes or flops per launch)."""
+    out = (ctypes.c_double * 2)()
+    _check(lib().ttsvd_machine_bench(kind, buf.data_ptr(), buf.numel() * buf.element_size(), reps,
+                                     _stream(stream), out))
+    return float(out[0]), float(out[1])
 
 
 def ttsvd_gemm_reshape(W, dtype: int, rows: int, cols: int, ld: int, V, ldv: int, k: int,

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libttsvd.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["api.hip", "tsqr.hip", "tsmm.hip", "svd.hip", "batch.hip", "server.hip", "thick.hip",
-           "profile.hip", "noalloc.hip"]
+           "profile.hip", "noalloc.hip", "machine.hip"]
 ARCH = os.environ.get("TTSVD_OFFLOAD_ARCH", "gfx950")
 
 

@@ -133,23 +133,100 @@ WsLayout ws_layout(const Footprint &f, size_t es) {
 
 }  // namespace
 
-// Keep freed stream-ordered allocations in the device's default pool instead
-// of returning them to the driver at every synchronisation, so repeated
-// decompositions reuse their multi-GiB workspaces.
-int keep_pool_memory(hipStream_t s) {
-    static std::mutex mu;
-    static bool done[64] = {false};
+namespace {
+struct CacheBlock {
+    void *p;
+    size_t bytes;
+    int dev;
+    bool busy;
+};
+std::mutex g_cache_mu;
+std::vector<CacheBlock> g_cache;
+constexpr size_t kCacheIdleBytes = size_t(32) << 30;  // idle memory kept per device
+
+// Frees idle blocks of device `dev`, largest first, until at most `keep`
+// idle bytes remain (called without the lock held).
+void cache_trim(int dev, size_t keep) {
+    std::vector<void *> drop;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        size_t idle = 0;
+        for (const CacheBlock &b : g_cache)
+            if (!b.busy && b.dev == dev) idle += b.bytes;
+        while (idle > keep) {
+            int big = -1;
+            for (int i = 0; i < (int)g_cache.size(); ++i)
+                if (!g_cache[i].busy && g_cache[i].dev == dev &&
+                    (big < 0 || g_cache[i].bytes > g_cache[big].bytes))
+                    big = i;
+            if (big < 0) break;
+            idle -= g_cache[big].bytes;
+            drop.push_back(g_cache[big].p);
+            g_cache.erase(g_cache.begin() + big);
+        }
+    }
+    for (void *p : drop) (void)hipFree(p);
+}
+
+void release_cb(void *p) { cache_release(p); }
+}  // namespace
+
+void *cache_acquire(size_t bytes) {
     int dev = 0;
-    TTSVD_HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(mu);
-    if (dev < 0 || dev >= 64 || done[dev]) return TTSVD_OK;
-    hipMemPool_t pool;
-    TTSVD_HIP_TRY(hipDeviceGetDefaultMemPool(&pool, dev));
-    uint64_t thr = UINT64_MAX;
-    TTSVD_HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
-    done[dev] = true;
-    (void)s;
-    return TTSVD_OK;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    bytes = align256(std::max<size_t>(bytes, 1));
+    {
+        // best fit among idle blocks that are not much larger than asked for
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        const size_t limit = std::max(2 * bytes, bytes + (size_t(64) << 20));
+        int best = -1;
+        for (int i = 0; i < (int)g_cache.size(); ++i) {
+            const CacheBlock &b = g_cache[i];
+            if (!b.busy && b.dev == dev && b.bytes >= bytes && b.bytes <= limit &&
+                (best < 0 || b.bytes < g_cache[best].bytes))
+                best = i;
+        }
+        if (best >= 0) {
+            g_cache[best].busy = true;
+            return g_cache[best].p;
+        }
+    }
+    cache_trim(dev, kCacheIdleBytes);  // bound the idle memory before growing
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        cache_trim(dev, 0);  // give idle blocks back and try once more
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache.push_back(CacheBlock{p, bytes, dev, true});
+    return p;
+}
+
+// (also called from host callbacks: no HIP calls here)
+void cache_release(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (CacheBlock &b : g_cache)
+        if (b.p == p) {
+            b.busy = false;
+            break;
+        }
+}
+
+hipError_t cache_release_async(void *p, hipStream_t s) {
+    return hipLaunchHostFunc(s, release_cb, p);
+}
+
+void *result_alloc(size_t bytes) { return cache_acquire(bytes); }
+
+void result_free(void *p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    cache_release(p);
 }
 
 void *pinned_stage(size_t bytes) {
@@ -240,8 +317,8 @@ int ttsvd_tsqr_r(const void *W, int dtype, int64_t rows, int64_t cols, int64_t l
     const size_t need = tsqr_workspace_bytes(dtype, rows, cols);
     void *own = nullptr;
     if (!ws) {
-        if (hipMallocAsync(&own, need, stream) != hipSuccess)
-            return set_error(TTSVD_ENOMEM, "tsqr_r: workspace of %zu bytes", need);
+        own = cache_acquire(need);
+        if (!own) return set_error(TTSVD_ENOMEM, "tsqr_r: workspace of %zu bytes", need);
         ws = own;
         ws_bytes = need;
     } else if (ws_bytes < need) {
@@ -249,9 +326,13 @@ int ttsvd_tsqr_r(const void *W, int dtype, int64_t rows, int64_t cols, int64_t l
     }
     int rc = tsqr_launch(W, dtype, rows, cols, ld, R, ldr, ws, ws_bytes, stream);
     if (own) {
-        hipError_t e = hipFreeAsync(own, stream);
-        if (rc == TTSVD_OK && e != hipSuccess)
-            rc = set_error(TTSVD_EHIP, "tsqr_r: hipFreeAsync: %s", hipGetErrorString(e));
+        // back to the cache once the launches before this point have run
+        hipError_t e = cache_release_async(own, stream);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(stream);
+            cache_release(own);
+            if (rc == TTSVD_OK) rc = set_error(TTSVD_EHIP, "tsqr_r: release: %s", hipGetErrorString(e));
+        }
     }
     return rc;
 }
@@ -285,9 +366,9 @@ void ttsvd_tt_free(ttsvd_tt *tt) {
     if (!tt) return;
     TTPriv *p = (TTPriv *)tt->priv;
     if (p) {
-        if (p->cores_dev) (void)hipFree(p->cores_dev);
+        if (p->cores_dev) result_free(p->cores_dev);
         if (p->shared && p->shared->refs.fetch_sub(1) == 1) {
-            (void)hipFree(p->shared->ptr);
+            result_free(p->shared->ptr);
             delete p->shared;
         }
         for (double *s : p->sigma_host) free(s);
@@ -332,10 +413,6 @@ static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int
 
     memset(out, 0, sizeof(*out));
     const hipStream_t s = X->stream;
-    if (!ws_in) {
-        rc = keep_pool_memory(s);
-        if (rc != TTSVD_OK) return rc;
-    }
 
     TTPriv *priv = new TTPriv();
     out->priv = priv;
@@ -344,7 +421,8 @@ static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int
 
     double *cores_base = cores_in;
     if (!cores_base) {
-        if (hipMalloc(&priv->cores_dev, std::max<size_t>(f.cores, 1) * 8) != hipSuccess) {
+        priv->cores_dev = (double *)result_alloc(std::max<size_t>(f.cores, 1) * 8);
+        if (!priv->cores_dev) {
             ttsvd_tt_free(out);
             return set_error(TTSVD_ENOMEM, "decompose: cores (%zu doubles)", f.cores);
         }
@@ -352,11 +430,12 @@ static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int
     }
     for (int i = 0; i < d; ++i) out->cores[i] = cores_base + f.core_off[i];
 
-    // One workspace for everything temporary: the caller's, or one
-    // stream-ordered allocation released before returning.
+    // One workspace for everything temporary: the caller's, or a library
+    // cache block released before returning (after the stream is synchronised).
     char *ws = (char *)ws_in;
     const bool own_ws = (ws == nullptr);
-    if (own_ws && hipMallocAsync((void **)&ws, lay.total, s) != hipSuccess) {
+    if (own_ws) ws = (char *)cache_acquire(lay.total);
+    if (own_ws && !ws) {
         ttsvd_tt_free(out);
         return set_error(TTSVD_ENOMEM, "decompose: workspace of %zu bytes", lay.total);
     }
@@ -374,9 +453,8 @@ static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int
     do {                                      \
         int rc_ = (expr);                     \
         if (rc_ != TTSVD_OK) {                \
-            if (own_ws)                       \
-                (void)hipFreeAsync(ws, s);    \
             (void)hipStreamSynchronize(s);    \
+            if (own_ws) cache_release(ws);    \
             ttsvd_tt_free(out);               \
             return rc_;                       \
         }                                     \
@@ -448,7 +526,7 @@ static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int
         TTSVD_STEP_HIP(hipMemcpyAsync(stage + align256(sizeof(hstate)), sig_dev, f.sigma * 8,
                                       hipMemcpyDeviceToHost, s));
     TTSVD_STEP_HIP(hipStreamSynchronize(s));
-    if (own_ws) TTSVD_STEP_HIP(hipFreeAsync(ws, s));
+    if (own_ws) cache_release(ws);
     memcpy(&hstate, stage, sizeof(hstate));
     std::vector<double> sig_host(std::max<size_t>(f.sigma, 1));
     if (f.sigma) memcpy(sig_host.data(), stage + align256(sizeof(hstate)), f.sigma * 8);

@@ -26,8 +26,23 @@ struct StepShape {
 int plan_steps(const int64_t *dims, int d, int64_t r_max, std::vector<StepShape> &steps,
                std::vector<int64_t> &rb, int64_t &nbar_out);
 
-// Keep freed stream-ordered allocations in the device's default pool.
-int keep_pool_memory(hipStream_t s);
+// Library-owned device buffers (workspaces and result cores): a per-device
+// cache of hipMalloc blocks reused across calls.  cache_acquire returns a
+// block of at least `bytes` bytes that no other call holds (NULL if the
+// allocation fails); cache_release hands it back, and the caller releases
+// only once no pending device work uses the block (after synchronising the
+// stream that used it, or from a host callback enqueued on that stream).
+// Blocks stay mapped between calls, so repeated calls neither map nor clear
+// memory; idle blocks beyond kCacheIdleBytes per device are freed.
+void *cache_acquire(size_t bytes);
+void cache_release(void *p);
+// cache_release enqueued on stream s: runs once the work before it is done.
+hipError_t cache_release_async(void *p, hipStream_t s);
+
+// Result cores: cache blocks released by ttsvd_tt_free after a device
+// synchronisation (so, as with hipFree, no pending work can still read them).
+void *result_alloc(size_t bytes);
+void result_free(void *p);
 
 // Pinned host staging buffer of at least `bytes` bytes owned by the calling
 // thread (grown on demand, kept for the thread's lifetime); device<->host

@@ -99,7 +99,8 @@ int ttsvd_decompose_thick(const ttsvd_tensor *X, const int64_t *dims, int d, int
     for (int i = 0; i < d; ++i)
         off[i + 1] = off[i] + (size_t)(out->ranks[i] * out->dims[i] * out->ranks[i + 1]);
     const hipStream_t s = X->stream;
-    hipError_t e = hipMalloc(&priv->cores_dev, std::max<size_t>(off[d], 1) * sizeof(double));
+    priv->cores_dev = (double *)result_alloc(std::max<size_t>(off[d], 1) * sizeof(double));
+    hipError_t e = priv->cores_dev ? hipSuccess : hipErrorOutOfMemory;
     for (int i = 0; i < d && e == hipSuccess; ++i) {
         out->cores[i] = priv->cores_dev + off[i];
         const double *src = i < d - k ? A.cores[i] : B.cores[i - (d - k)];

@@ -282,6 +282,14 @@ std::vector<Level> plan(int64_t rows, int64_t m) {
 
 size_t level_out_doubles(const Level &l, int64_t m) { return (size_t)(l.nslices * m) * (size_t)m; }
 
+// Sizes (doubles) of the two ping-pong buffers of the stacked factors: level i
+// (all but the last, which writes R) writes buffer i mod 2.
+void level_buffers(const std::vector<Level> &lv, int64_t m, size_t buf[2]) {
+    buf[0] = buf[1] = 0;
+    for (size_t i = 0; i + 1 < lv.size(); ++i)
+        buf[i & 1] = std::max(buf[i & 1], level_out_doubles(lv[i], m));
+}
+
 template <typename Tin>
 int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level &l,
                      double *out, int64_t ld_out, int64_t out_stride, int kvalid,
@@ -383,24 +391,24 @@ int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Le
 size_t tsqr_workspace_bytes(int dtype, int64_t rows, int64_t m) {
     (void)dtype;
     std::vector<Level> lv = plan(rows, m);
-    size_t buf = 0, rws = 0;
-    for (size_t i = 0; i + 1 < lv.size(); ++i) buf = std::max(buf, level_out_doubles(lv[i], m));
+    size_t buf[2] = {0, 0}, rws = 0;
+    level_buffers(lv, m, buf);
     if (m > 128)
         for (const Level &l : lv) rws = std::max(rws, (size_t)(l.nslices * m) * (size_t)m);
-    return (2 * buf + rws) * sizeof(double) + 256;
+    return (buf[0] + buf[1] + rws) * sizeof(double) + 256;
 }
 
 int tsqr_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, double *R,
                 int64_t ldr, void *ws, size_t ws_bytes, hipStream_t s) {
     if (m > 1024) return set_error(TTSVD_EUNSUPPORTED, "tsqr: cols = %lld > 1024", (long long)m);
     std::vector<Level> lv = plan(rows, m);
-    size_t buf = 0;
-    for (size_t i = 0; i + 1 < lv.size(); ++i) buf = std::max(buf, level_out_doubles(lv[i], m));
+    size_t buf[2] = {0, 0};
+    level_buffers(lv, m, buf);
     if (ws_bytes < tsqr_workspace_bytes(dtype, rows, m))
         return set_error(TTSVD_EINVAL, "tsqr: workspace too small");
     double *b0 = (double *)ws;
-    double *b1 = b0 + buf;
-    double *rws = b1 + buf;
+    double *b1 = b0 + buf[0];
+    double *rws = b1 + buf[1];
     const int kvalid = (int)std::min<int64_t>(rows, m);
     const double *in = nullptr;
     for (size_t i = 0; i < lv.size(); ++i) {

@@ -133,14 +133,17 @@ def test_batch_zero_and_rank_one_tensors():
     assert res[1].ranks == [1, 1, 1, 1]
 
 
-def test_batch_fp32_storage_within_precision_bound():
+@pytest.mark.parametrize("tile_set", [0, 1])
+def test_batch_fp32_storage_within_precision_bound(tile_set):
     specs = [([2] * 14, 7), ([4, 4, 4, 4, 4, 4], 5), ([8, 2, 4, 2, 8], 6), ([2, 4, 8, 4, 2, 2], 3)]
     cases = []
     for i, (dims, rank) in enumerate(specs):
         X = synth.exact_tt(dims, rank, seed=70 + i, noise=1e-6, noise_seed=80 + i,
                            unit_variance=True, relative_noise=True)
         cases.append((dims, 16, 1e-5, X))
-    res, Xs = run_batch(cases, dtype=torch.float32)
+    cfg = tt.batch_default_config()
+    cfg.tile_set = tile_set          # 1: half the rows per lane (built for FP32)
+    res, Xs = run_batch(cases, dtype=torch.float32, cfg=cfg)
     u = 2.0 ** -24
     for (dims, r_max, tol, X), g, Xd in zip(cases, res, Xs):
         Xs64 = Xd.to(torch.float64).cpu().numpy()
@@ -185,7 +188,29 @@ def test_batch_errors():
     with pytest.raises(tt.TTSVDError) as e:
         tt.ttsvd_decompose_batch([X], [[4, 16]], 0, 0.0)
     assert e.value.code == -1
+    cfg = tt.batch_default_config()
+    cfg.tile_set = 1                                           # built for FP32 only
+    with pytest.raises(tt.TTSVDError) as e:
+        tt.ttsvd_decompose_batch([X], [[4, 16]], 3, 0.0, cfg=cfg)
+    assert e.value.code == -5
     bad = torch.tensor([1.0, float("nan")] * 8, dtype=torch.float64, device=DEV)
     with pytest.raises(tt.TTSVDError) as e:
         tt.ttsvd_decompose_batch([X, bad], [[4, 16], [2, 2, 4]], 3, 0.0)
     assert e.value.code == -4
+
+
+def test_batch_repeated_calls_release_cheaply():
+    # Regression: per-call hipMalloc/hipFree of the shared core buffer once made
+    # every release cost ~240 ms after a few dozen calls in one process.  The
+    # binding releases the results inside the call, so the call time shows it.
+    import time
+    cases = mixed_batch()[:4]
+    Xs = [dev(X) for (_, _, _, X) in cases]
+    dims = [c[0] for c in cases]
+    ts = []
+    for _ in range(40):
+        t0 = time.perf_counter()
+        tt.ttsvd_decompose_batch(Xs, dims, [c[1] for c in cases], [c[2] for c in cases],
+                                 fetch=False)
+        ts.append(time.perf_counter() - t0)
+    assert max(ts[10:]) < 4 * float(np.median(ts[:10])) + 0.02, (np.median(ts[:10]), max(ts[10:]))
