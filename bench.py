@@ -538,6 +538,34 @@ def small_latency(tt, steps, warmup):
             "mean_us": round(sec * 1e6, 1), "calls": n, "ranks": res.ranks}
 
 
+def alg1_comparator(tt, d=24, r_max=32):
+    """Algorithm 1 (full SVD of every unfolding, rocSOLVER GESVD without QR
+    preprocessing) against Algorithm 2 on the same 2^d U[0,1) FP64 tensor
+    (d modes of size 2, r_max, no tol): the speed-up of the QR trick."""
+    import numpy as np
+    import torch
+    X = torch.from_numpy(np.random.default_rng(0).random(2 ** d)).to("cuda:0")
+    dims = [2] * d
+    tt.ttsvd_decompose_alg1(X, dims, r_max, 0.0)          # warm-up
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        g1 = tt.ttsvd_decompose_alg1(X, dims, r_max, 0.0)
+        ts.append(time.perf_counter() - t0)
+    t1 = sorted(ts)[1]
+    sec2, g2, med2 = time_decompose(tt, X, dims, r_max, 0.0, 10, 2)
+    dev = max(float(np.max(np.abs(np.asarray(g1.sigma[j]) - np.asarray(g2.sigma[j])))) /
+              float(g1.sigma[j][0]) for j in range(1, d))
+    del X
+    torch.cuda.empty_cache()
+    return {"workload": "2^%d U[0,1) FP64, d=%d, n_i=2, r_max=%d, no tol" % (d, d, r_max),
+            "alg1_ms": round(t1 * 1e3, 2), "alg2_ms": round(med2 * 1e3, 3),
+            "qr_trick_speedup": round(t1 / med2, 1), "ranks_equal": g1.ranks == g2.ranks,
+            "max_sigma_dev_rel_sigma1": dev,
+            "paper_context": "about 50x for TSQR with the QR trick against a plain LAPACK SVD "
+                             "(10^7 x m, m <= 50, one 14-core Skylake-SP socket)"}
+
+
 def sweeps(tt):
     """GB/s and TFLOP/s of ttsvd_tsqr_r and ttsvd_gemm_reshape against the
     column count m on 1 GiB FP64 inputs (rows = 2^27 / m; the product has
@@ -597,6 +625,7 @@ def main():
     ap.add_argument("--no-machine", action="store_true")
     ap.add_argument("--no-sweeps", action="store_true")
     ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-alg1", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -686,6 +715,9 @@ def main():
     if not args.no_small:
         line["small_latency"] = small_latency(tt, args.steps, args.warmup)
         log("small workload: %s" % line["small_latency"])
+    if not args.no_alg1:
+        line["alg1_comparator"] = alg1_comparator(tt)
+        log("alg1 comparator: %s" % line["alg1_comparator"])
     if not args.no_sweeps:
         line["sweeps"] = sweeps(tt)
         log("sweeps: %s" % line["sweeps"])

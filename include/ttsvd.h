@@ -181,6 +181,22 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d,
                     int64_t r_max, double tol, ttsvd_tt *out);
 
 /*
+ * ttsvd_decompose_alg1 -- Algorithm 1 (the original TT-SVD, Sec. 3.1.1) on
+ * the GPU, the in-house comparator that measures what the QR trick of
+ * Algorithm 2 saves.  Every step takes the full SVD of the unfolding W^(i)
+ * itself (rocSOLVER GESVD with its QR preprocessing off), the rank rule with
+ * delta = eps/sqrt(d-1) ||X||_F (||X||_F^2 from the first step's singular
+ * values), core T^(i) = reshape(V_r^T) and W^(i-1) = reshape(U_r Sigma_r).
+ * Same arguments and result as ttsvd_decompose; FP64 input only, dense last
+ * mode (ld_last 0 or equal to the leading extent), every unfolding within
+ * 32-bit rocSOLVER sizes.  Synchronises X->stream.  Errors: TTSVD_EINVAL,
+ * TTSVD_EUNSUPPORTED (dtype, padded stride, sizes), TTSVD_ENOMEM, TTSVD_EHIP
+ * (also when GESVD does not converge), TTSVD_ENONFINITE.
+ */
+int ttsvd_decompose_alg1(const ttsvd_tensor *X, const int64_t *dims, int d,
+                         int64_t r_max, double tol, ttsvd_tt *out);
+
+/*
  * Caller-provided buffers for ttsvd_decompose (Algorithm 2, whose REQUIRE /
  * ENSURE clauses fix the inputs and outputs; the buffers are only where the
  * intermediate unfoldings W^(i) and the cores T^(i) live).

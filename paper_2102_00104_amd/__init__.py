@@ -35,7 +35,7 @@ EXPORTED = ["ttsvd_tsqr_r", "ttsvd_tsqr_workspace_size", "ttsvd_gemm_reshape",
             "ttsvd_server_poll", "ttsvd_server_pending", "ttsvd_server_destroy",
             "ttsvd_server_clock", "ttsvd_thick_bounds_k", "ttsvd_decompose_thick",
             "ttsvd_workspace_size", "ttsvd_cores_size", "ttsvd_decompose_ws",
-            "ttsvd_tsqr_r_noalloc", "ttsvd_machine_bench"]
+            "ttsvd_tsqr_r_noalloc", "ttsvd_machine_bench", "ttsvd_decompose_alg1"]
 
 
 class TTSVDError(RuntimeError):
@@ -147,6 +147,9 @@ def lib() -> ctypes.CDLL:
         L.ttsvd_decompose.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64), ctypes.c_int,
                                       i64, ctypes.c_double, ctypes.POINTER(TTStruct)]
         L.ttsvd_decompose.restype = ctypes.c_int
+        L.ttsvd_decompose_alg1.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64),
+                                           ctypes.c_int, i64, ctypes.c_double, ctypes.POINTER(TTStruct)]
+        L.ttsvd_decompose_alg1.restype = ctypes.c_int
         L.ttsvd_workspace_size.argtypes = [ctypes.POINTER(i64), ctypes.c_int, i64, ctypes.c_int]
         L.ttsvd_workspace_size.restype = ctypes.c_size_t
         L.ttsvd_cores_size.argtypes = [ctypes.POINTER(i64), ctypes.c_int, i64]
@@ -353,6 +356,23 @@ def ttsvd_decompose(X, dims: Sequence[int], r_max: int, tol: float, ld_last: int
     arr = (ctypes.c_int64 * d)(*dims)
     out = TTStruct()
     _check(lib().ttsvd_decompose(ctypes.byref(xs), arr, d, r_max, float(tol), ctypes.byref(out)))
+    try:
+        return _to_tt(out, X.device, st)
+    finally:
+        lib().ttsvd_tt_free(ctypes.byref(out))
+
+
+def ttsvd_decompose_alg1(X, dims: Sequence[int], r_max: int, tol: float, stream=None) -> TT:
+    """``ttsvd_decompose_alg1``: Algorithm 1 (full SVD of every unfolding, no
+    QR trick) on the GPU, the comparator for Algorithm 2 (FP64 only)."""
+    dims = [int(n) for n in dims]
+    d = len(dims)
+    st = _stream(stream)
+    xs = TensorStruct(X.data_ptr(), dtype_code(X), 0, st)
+    arr = (ctypes.c_int64 * d)(*dims)
+    out = TTStruct()
+    _check(lib().ttsvd_decompose_alg1(ctypes.byref(xs), arr, d, r_max, float(tol),
+                                      ctypes.byref(out)))
     try:
         return _to_tt(out, X.device, st)
     finally:

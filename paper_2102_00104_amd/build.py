@@ -19,8 +19,11 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libttsvd.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["api.hip", "tsqr.hip", "tsmm.hip", "svd.hip", "batch.hip", "server.hip", "thick.hip",
-           "profile.hip", "noalloc.hip", "machine.hip"]
+           "profile.hip", "noalloc.hip", "machine.hip",
+           "alg1.hip"]
 ARCH = os.environ.get("TTSVD_OFFLOAD_ARCH", "gfx950")
+# rocSOLVER / rocBLAS serve only the Algorithm 1 comparator (alg1.hip)
+LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
 
 
 def hipcc() -> str:
@@ -60,7 +63,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + LIBS
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (res.stdout, res.stderr))

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "ttsvd.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ttsvd_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(ttsvd_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_matches_binding_list():
