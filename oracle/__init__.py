@@ -25,6 +25,9 @@ of the paper):
 * ``ttsvd_thick`` -- Algorithm 3 (thick-bounds TT-SVD): Algorithm 2 on the
                      tensor with its k right-most modes combined, then the
                      combined core split by a TT-SVD of its own.
+* ``ttsvd_two_sided`` -- Algorithm 4 (two-sided TSQR TT-SVD): steps on the
+                     right-most and the left-most remaining mode in turn; a
+                     left step takes the QR of the transposed left unfolding.
 * ``tt_full``     -- contraction of the TT cores back to a dense tensor
                      (the TT format, Sec. 2.1.2).
 
@@ -255,6 +258,91 @@ def ttsvd(X: np.ndarray, dims: Sequence[int], r_max: int, tol: float,
         ranks[i] = r
         W = np.asfortranarray(Wn).reshape(-1, order="F")
     cores[0] = W.reshape(1, dims[0], ranks[1], order="F").copy(order="F")
+    return OracleTT(dims, ranks, cores, sigmas, disc, delta, norm_sigma, margins)
+
+
+def ttsvd_two_sided(X: np.ndarray, dims: Sequence[int], r_max: int, tol: float) -> OracleTT:
+    """Two-sided TSQR TT-SVD (Algorithm 4).
+
+    The remaining tensor Y has modes lo..hi (0-based) with bond ranks
+    r_lo on its left and r_{hi+1} on its right, Fortran-ordered.  Steps
+    alternate, starting on the right (the paper's i = d, 1, d-1, 2, ...):
+
+    * right step on mode hi: W = reshape(Y, (rest, n_hi r_{hi+1})); R from the
+      QR of W; SVD of R; r_hi by the rank rule; T^(hi) = reshape(V_r^T);
+      Y <- W V_r;
+    * left step on mode lo: L = reshape(Y, (r_lo n_lo, rest)) is short and
+      wide, so the QR is taken of its transpose L^T (the reordering of
+      Algorithm 4); SVD of R = U S V^T gives L = V S (Q U)^T, so
+      T^(lo) = reshape(V_r, (r_lo, n_lo, r_{lo+1})) and the remainder is
+      (L^T V_r)^T.
+
+    delta comes from the first step's ||Sigma||_F as in Algorithm 2.  The last
+    remaining mode is the middle core.  sigma[j] and discarded2[j] belong to
+    the step that chose ranks[j] (j = 1..d-1), as for ``ttsvd``.
+    """
+    dims = [int(n) for n in dims]
+    d = len(dims)
+    if d < 1 or any(n < 1 for n in dims) or r_max < 1 or tol < 0:
+        raise ValueError("invalid TT-SVD arguments")
+    X = np.asarray(X, dtype=np.float64).reshape(-1, order="F")
+    if X.size != _prod(dims):
+        raise ValueError("X has %d elements, dims need %d" % (X.size, _prod(dims)))
+    if d == 1:
+        return ttsvd(X, dims, r_max, tol)
+    ranks = [1] * (d + 1)
+    cores: List[Optional[np.ndarray]] = [None] * d
+    sigmas: List[Optional[np.ndarray]] = [None] * d
+    disc = [0.0] * d
+    margins = [math.inf] * d
+    delta = 0.0
+    norm_sigma = 0.0
+    first = True
+    Y = X.copy()
+    lo, hi = 0, d - 1
+    right = True
+    while lo < hi:
+        if right:
+            m = dims[hi] * ranks[hi + 1]
+            rows = Y.size // m
+            W = Y.reshape(rows, m, order="F")
+            bond = hi
+        else:
+            P = ranks[lo] * dims[lo]
+            Q = Y.size // P
+            W = np.asfortranarray(Y.reshape(P, Q, order="F").T)      # L^T, Q x P
+            rows, m = Q, P
+            bond = lo + 1
+        K = min(rows, m)
+        R = qr_r(W)
+        sigma, V = jacobi_svd(R)
+        sigma = sigma[:K].copy()
+        if first:
+            norm_sigma = float(np.sqrt(np.sum(sigma * sigma)))
+            delta = tol / math.sqrt(d - 1) * norm_sigma
+            first = False
+        r = rank_rule(sigma, delta, r_max, tol)
+        t = tails(sigma)
+        disc[bond] = float(t[r])
+        if tol > 0:
+            d2 = delta * delta
+            cand = [abs(t[r] - d2) / d2 if d2 > 0 else math.inf]
+            if r >= 1:
+                cand.append(abs(t[r - 1] - d2) / d2 if d2 > 0 else math.inf)
+            margins[bond] = min(cand)
+        sigmas[bond] = sigma
+        ranks[bond] = r
+        Wbar = W @ V[:, :r]                                          # rows x r
+        if right:
+            cores[hi] = V[:, :r].T.reshape(r, dims[hi], ranks[hi + 1], order="F").copy(order="F")
+            Y = np.asfortranarray(Wbar).reshape(-1, order="F")
+            hi -= 1
+        else:
+            cores[lo] = V[:, :r].reshape(ranks[lo], dims[lo], r, order="F").copy(order="F")
+            Y = np.asfortranarray(Wbar.T).reshape(-1, order="F")
+            lo += 1
+        right = not right
+    cores[lo] = Y.reshape(ranks[lo], dims[lo], ranks[lo + 1], order="F").copy(order="F")
     return OracleTT(dims, ranks, cores, sigmas, disc, delta, norm_sigma, margins)
 
 
