@@ -538,6 +538,60 @@ def small_latency(tt, steps, warmup):
             "mean_us": round(sec * 1e6, 1), "calls": n, "ranks": res.ranks}
 
 
+def two_sided(tt, model, X, dims, r_max, steps, warmup, plain_sec, plain_res):
+    """Algorithm 4 (two-sided) on the resident tensor: time per decomposition
+    (C call with prebuilt arguments), its effective GB/s over its own
+    algorithmic bytes (TSQR read + TSMM read/write of every step, plus the
+    transposes' read and write of the remainder), and its result beside the
+    plain one's."""
+    import ctypes
+
+    import numpy as np
+    import torch
+    L = tt.lib()
+    d = len(dims)
+    st = torch.cuda.current_stream().cuda_stream
+    xs = tt.TensorStruct(X.data_ptr(), tt.dtype_code(X), 0, st)
+    arr = (ctypes.c_int64 * d)(*dims)
+    out = tt.TTStruct()
+
+    def once():
+        rc = L.ttsvd_decompose_two_sided(ctypes.byref(xs), arr, d, r_max, 0.0, ctypes.byref(out))
+        if rc != 0:
+            raise tt.TTSVDError(rc, L.ttsvd_last_error().decode())
+        L.ttsvd_tt_free(ctypes.byref(out))
+    for _ in range(warmup):
+        once()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        once()
+        ts.append(time.perf_counter() - t0)
+    med = sorted(ts)[len(ts) // 2]
+    g = tt.ttsvd_decompose_two_sided(X, dims, r_max, 0.0)
+    # algorithmic bytes of the two-sided order at the ranks it chose
+    e = X.element_size()
+    size, lo, hi, right, ab = X.numel(), 0, d - 1, True, 0.0
+    while lo < hi:
+        m = dims[hi] * g.ranks[hi + 1] if right else g.ranks[lo] * dims[lo]
+        r = g.ranks[hi] if right else g.ranks[lo + 1]
+        nxt = size // m * r
+        last = (hi - 1 == lo) if right else (lo + 1 == hi)
+        ab += e * (2 * size + nxt) + (0 if last else 2 * e * nxt)
+        size = nxt
+        if right:
+            hi -= 1
+        else:
+            lo += 1
+        right = not right
+    return {"ms_per_step": round(med * 1e3, 3), "value": round(ab / med / 1e9, 2), "unit": "GB/s",
+            "algorithmic_bytes": ab, "speedup_vs_plain": round(plain_sec / med, 3),
+            "ranks": g.ranks, "ranks_equal_plain": g.ranks == plain_res.ranks,
+            "err_bound_rel": g.err_bound / g.norm_sigma,
+            "plain_err_bound_rel": plain_res.err_bound / plain_res.norm_sigma}
+
+
 def alg1_comparator(tt, d=24, r_max=32):
     """Algorithm 1 (full SVD of every unfolding, rocSOLVER GESVD without QR
     preprocessing) against Algorithm 2 on the same 2^d U[0,1) FP64 tensor
@@ -626,6 +680,7 @@ def main():
     ap.add_argument("--no-sweeps", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-alg1", action="store_true")
+    ap.add_argument("--no-two-sided", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -727,6 +782,10 @@ def main():
     if not args.no_thick:
         line["thick_bounds"] = thick_bounds(tt, model, X, head["dims"], args.r_max, args.steps,
                                             args.warmup, head["sec"], head["res"])
+    if not args.no_two_sided:
+        line["two_sided"] = two_sided(tt, model, X, head["dims"], args.r_max, max(args.steps, 5),
+                                      args.warmup, head["sec"], head["res"])
+        log("two-sided: %s" % line["two_sided"])
     if not args.no_batched:
         line["batched"] = batched(tt, args.steps, args.warmup)
     if not args.no_serving:

@@ -181,6 +181,24 @@ int ttsvd_decompose(const ttsvd_tensor *X, const int64_t *dims, int d,
                     int64_t r_max, double tol, ttsvd_tt *out);
 
 /*
+ * ttsvd_decompose_two_sided -- the two-sided TSQR TT-SVD (Algorithm 4,
+ * Sec. 3.1.3).  Steps alternate between the right-most and the left-most
+ * remaining mode (i = d, 1, d-1, 2, ...); a left step takes the Q-less TSQR
+ * of the transposed left unfolding, and the remainder is reordered by a
+ * transpose between steps.  delta comes from the first step's ||Sigma||_F as
+ * in Algorithm 2.  Same arguments and result as ttsvd_decompose, except that
+ * sigma[j], nsigma[j] and discarded2[j] belong to the step that chose
+ * ranks[j] (for j > the middle core these are the right steps, as in
+ * ttsvd_decompose); cores left of the middle have orthonormal columns as
+ * (r_{j-1} n_j) x r_j matrices, cores right of it orthonormal rows.  d <= 2
+ * is Algorithm 2 itself.  Every step must have at most 1024 columns and keep
+ * at most 256 (rank upper bounds); dense last mode only.  Synchronises
+ * X->stream.  Errors as ttsvd_decompose (TTSVD_EUNSUPPORTED for the limits).
+ */
+int ttsvd_decompose_two_sided(const ttsvd_tensor *X, const int64_t *dims, int d,
+                              int64_t r_max, double tol, ttsvd_tt *out);
+
+/*
  * ttsvd_decompose_alg1 -- Algorithm 1 (the original TT-SVD, Sec. 3.1.1) on
  * the GPU, the in-house comparator that measures what the QR trick of
  * Algorithm 2 saves.  Every step takes the full SVD of the unfolding W^(i)

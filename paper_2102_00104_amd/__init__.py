@@ -35,7 +35,8 @@ EXPORTED = ["ttsvd_tsqr_r", "ttsvd_tsqr_workspace_size", "ttsvd_gemm_reshape",
             "ttsvd_server_poll", "ttsvd_server_pending", "ttsvd_server_destroy",
             "ttsvd_server_clock", "ttsvd_thick_bounds_k", "ttsvd_decompose_thick",
             "ttsvd_workspace_size", "ttsvd_cores_size", "ttsvd_decompose_ws",
-            "ttsvd_tsqr_r_noalloc", "ttsvd_machine_bench", "ttsvd_decompose_alg1"]
+            "ttsvd_tsqr_r_noalloc", "ttsvd_machine_bench", "ttsvd_decompose_alg1",
+            "ttsvd_decompose_two_sided"]
 
 
 class TTSVDError(RuntimeError):
@@ -150,6 +151,10 @@ def lib() -> ctypes.CDLL:
         L.ttsvd_decompose_alg1.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64),
                                            ctypes.c_int, i64, ctypes.c_double, ctypes.POINTER(TTStruct)]
         L.ttsvd_decompose_alg1.restype = ctypes.c_int
+        L.ttsvd_decompose_two_sided.argtypes = [ctypes.POINTER(TensorStruct), ctypes.POINTER(i64),
+                                                ctypes.c_int, i64, ctypes.c_double,
+                                                ctypes.POINTER(TTStruct)]
+        L.ttsvd_decompose_two_sided.restype = ctypes.c_int
         L.ttsvd_workspace_size.argtypes = [ctypes.POINTER(i64), ctypes.c_int, i64, ctypes.c_int]
         L.ttsvd_workspace_size.restype = ctypes.c_size_t
         L.ttsvd_cores_size.argtypes = [ctypes.POINTER(i64), ctypes.c_int, i64]
@@ -373,6 +378,24 @@ def ttsvd_decompose_alg1(X, dims: Sequence[int], r_max: int, tol: float, stream=
     out = TTStruct()
     _check(lib().ttsvd_decompose_alg1(ctypes.byref(xs), arr, d, r_max, float(tol),
                                       ctypes.byref(out)))
+    try:
+        return _to_tt(out, X.device, st)
+    finally:
+        lib().ttsvd_tt_free(ctypes.byref(out))
+
+
+def ttsvd_decompose_two_sided(X, dims: Sequence[int], r_max: int, tol: float,
+                              stream=None) -> TT:
+    """``ttsvd_decompose_two_sided``: Algorithm 4 (steps alternately on the
+    right-most and the left-most remaining mode)."""
+    dims = [int(n) for n in dims]
+    d = len(dims)
+    st = _stream(stream)
+    xs = TensorStruct(X.data_ptr(), dtype_code(X), 0, st)
+    arr = (ctypes.c_int64 * d)(*dims)
+    out = TTStruct()
+    _check(lib().ttsvd_decompose_two_sided(ctypes.byref(xs), arr, d, r_max, float(tol),
+                                           ctypes.byref(out)))
     try:
         return _to_tt(out, X.device, st)
     finally:

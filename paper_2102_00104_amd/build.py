@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libttsvd.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["api.hip", "tsqr.hip", "tsmm.hip", "svd.hip", "batch.hip", "server.hip", "thick.hip",
            "profile.hip", "noalloc.hip", "machine.hip",
-           "alg1.hip"]
+           "alg1.hip", "twosided.hip"]
 ARCH = os.environ.get("TTSVD_OFFLOAD_ARCH", "gfx950")
 # rocSOLVER / rocBLAS serve only the Algorithm 1 comparator (alg1.hip)
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
