@@ -358,12 +358,15 @@ int ttsvd_batch_autotune(int count, const ttsvd_tensor *X, const int *d,
                          ttsvd_batch_config *best, double *best_ms);
 
 /*
- * Serving runtime: requests that arrive over time are queued in FIFO order,
- * admitted while the sum of their device footprints (ttsvd_footprint_bytes)
- * stays within a budget, and run by worker threads, each on its own stream.
- * Small requests (every step at most 128 columns, at most batch_max_elems
- * elements, dense) waiting together are decomposed in one batched launch;
- * the others run alone.  Timestamps are seconds of ttsvd_server_clock().
+ * Serving runtime: requests that arrive over time are admitted while the sum
+ * of their device footprints (ttsvd_footprint_bytes) stays within a budget
+ * and run by worker threads, each on its own stream.  Continuous batching:
+ * small requests (every step at most 128 columns, at most batch_max_elems
+ * elements, dense) wait in their own FIFO, and whenever no batched launch is
+ * running a free worker decomposes all of them that fit (up to max_batch) in
+ * one batched launch, so requests arriving meanwhile join the next one.  The
+ * other requests wait in FIFO order and run alone on the other workers.
+ * Timestamps are seconds of ttsvd_server_clock().
  */
 typedef struct ttsvd_server ttsvd_server;
 

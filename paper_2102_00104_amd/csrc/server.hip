@@ -2,15 +2,17 @@
 // arrive over time, admitted by their device-memory footprint and executed by
 // worker threads, each on its own HIP stream (default priority).
 //
-// Scheduling: requests wait in FIFO order.  A free worker takes the head
-// request if its footprint fits the memory budget next to the requests
-// already running; if the head is small (every TT step of at most 128
-// columns and at most batch_max_elems elements) it also takes the following
-// small requests that fit, up to max_batch, and runs them together in one
-// persistent batched launch (ttsvd_decompose_batch).  Other requests run
-// alone (ttsvd_decompose).  Workers that finish return their footprint and
-// wake the others, so admitted work starts as soon as memory frees up; a
-// head that does not fit blocks the queue (no reordering, no starvation).
+// Scheduling (continuous batching): small requests (every TT step of at
+// most 128 columns, at most batch_max_elems elements, dense) wait in their own
+// FIFO; whenever no batched launch is running, a free worker takes every
+// waiting small request that fits the memory budget (up to max_batch) and
+// runs them together in one persistent batched launch
+// (ttsvd_decompose_batch), so requests that arrive while a batch runs join
+// the next one.  Other requests wait in a second FIFO and run alone
+// (ttsvd_decompose) on the other workers as their footprint fits the budget
+// next to the running work; a large head that does not fit blocks only the
+// large FIFO.  Workers that finish return their footprint and wake the
+// others, so admitted work starts as soon as memory frees up.
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
@@ -55,7 +57,9 @@ struct ttsvd_server {
     std::mutex mu;
     std::condition_variable cv_work;   // workers: new requests or freed memory
     std::condition_variable cv_done;   // pollers: new completions
-    std::deque<ttsvd::Request> queue;
+    std::deque<ttsvd::Request> queue;        // large requests, FIFO
+    std::deque<ttsvd::Request> small_queue;  // small requests, FIFO
+    bool batch_running = false;
     std::deque<ttsvd_completion> done;
     std::vector<std::thread> workers;
     size_t in_use = 0;
@@ -86,36 +90,46 @@ void worker_main(ttsvd_server *S) {
     for (;;) {
         take.clear();
         size_t claimed = 0;
+        bool as_batch = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             for (;;) {
-                if (S->stop && S->queue.empty()) break;
+                if (S->stop && S->queue.empty() && S->small_queue.empty()) break;
+                if (!S->small_queue.empty() && !S->batch_running) {
+                    const Request &h = S->small_queue.front();
+                    if (S->in_use + h.footprint <= S->cfg.hbm_budget || S->in_use == 0) {
+                        as_batch = true;
+                        break;
+                    }
+                }
                 if (!S->queue.empty()) {
                     const Request &h = S->queue.front();
                     // a request larger than the whole budget runs alone once nothing else runs
-                    const bool fits = S->in_use + h.footprint <= S->cfg.hbm_budget || S->in_use == 0;
-                    if (fits) break;
+                    if (S->in_use + h.footprint <= S->cfg.hbm_budget || S->in_use == 0) break;
                 }
                 S->cv_work.wait(lk);
             }
-            if (S->queue.empty()) break;  // stopping
-            take.push_back(S->queue.front());
-            S->queue.pop_front();
-            claimed = take[0].footprint;
-            if (take[0].small && S->cfg.max_batch > 1) {
-                for (auto it = S->queue.begin();
-                     it != S->queue.end() && (int)take.size() < S->cfg.max_batch;) {
-                    if (it->small && it->X.dtype == take[0].X.dtype &&
-                        S->in_use + claimed + it->footprint <= S->cfg.hbm_budget) {
+            if (S->queue.empty() && S->small_queue.empty()) break;  // stopping
+            if (as_batch) {
+                // every waiting small request that fits, in arrival order
+                S->batch_running = true;
+                for (auto it = S->small_queue.begin();
+                     it != S->small_queue.end() && (int)take.size() < S->cfg.max_batch;) {
+                    const bool first = take.empty();
+                    if (it->X.dtype == S->small_queue.front().X.dtype &&
+                        (S->in_use + claimed + it->footprint <= S->cfg.hbm_budget ||
+                         (first && S->in_use == 0))) {
                         claimed += it->footprint;
                         take.push_back(*it);
-                        it = S->queue.erase(it);
-                    } else if (!it->small) {
-                        break;  // keep FIFO order relative to large requests
+                        it = S->small_queue.erase(it);
                     } else {
                         ++it;
                     }
                 }
+            } else {
+                take.push_back(S->queue.front());
+                S->queue.pop_front();
+                claimed = take[0].footprint;
             }
             S->in_use += claimed;
         }
@@ -132,14 +146,14 @@ void worker_main(ttsvd_server *S) {
             comp[i].t_submit = take[i].t_submit;
             comp[i].t_start = t_start;
             comp[i].batch_size = (int)take.size();
-            comp[i].batched = !(take.size() == 1 && !(take[0].small && S->cfg.max_batch > 1));
+            comp[i].batched = as_batch;
         }
         if (!waited) {
             for (auto &c : comp) {
                 c.status = TTSVD_EHIP;
                 snprintf(c.message, sizeof(c.message), "server: worker stream or event wait failed");
             }
-        } else if (take.size() == 1 && !(take[0].small && S->cfg.max_batch > 1)) {
+        } else if (!as_batch) {
             ttsvd_tensor X = take[0].X;
             X.stream = st;
             comp[0].status = ttsvd_decompose(&X, take[0].dims.data(), (int)take[0].dims.size(),
@@ -179,6 +193,7 @@ void worker_main(ttsvd_server *S) {
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->in_use -= claimed;
+            if (as_batch) S->batch_running = false;
             for (auto &c : comp) {
                 c.t_done = t_done;
                 S->done.push_back(c);
@@ -256,7 +271,11 @@ int ttsvd_server_submit(ttsvd_server *S, const ttsvd_tensor *X, const int64_t *d
         }
         r.ticket = S->next_ticket++;
         *ticket = r.ticket;
-        S->queue.push_back(std::move(r));
+        // small requests go to the batching lane unless batching is off
+        if (r.small && S->cfg.max_batch > 1)
+            S->small_queue.push_back(std::move(r));
+        else
+            S->queue.push_back(std::move(r));
         S->pending += 1;
     }
     S->cv_work.notify_one();

@@ -130,3 +130,34 @@ def test_trace_requests_with_shrinking_ranks(idx):
         o = oracle.ttsvd(Xh, q["dims"], q["r_max"], q["tol"])
         if min(o.margins[1:]) > 1e-2:
             assert g.ranks == o.ranks
+
+
+def test_server_small_requests_batch_while_large_ones_wait():
+    # Continuous batching: small requests that arrive while large ones hold the
+    # memory budget (the second large one waits for the first) are batched
+    # together on another worker and finish before the waiting large request
+    # starts; their results equal the batched path alone.
+    big = []
+    for i in range(2):
+        dims = [16] * 6
+        X = synth.exact_tt_device(dims, synth.capped_ranks(dims, 6), seed=600 + i, noise=1e-6,
+                                  noise_seed=610 + i, device=DEV, dtype=torch.float64)
+        big.append((dims, 32, 0.0, X))
+    small = []
+    for i in range(8):
+        dims = [2] * 14
+        X = synth.exact_tt_device(dims, synth.capped_ranks(dims, 4), seed=620 + i, noise=1e-6,
+                                  noise_seed=630 + i, device=DEV, dtype=torch.float64)
+        small.append((dims, 8, 1e-4, X))
+    fb = tt.ttsvd_footprint_bytes(big[0][0], 32, tt.TTSVD_F64)
+    fs = sum(tt.ttsvd_footprint_bytes(d, r, tt.TTSVD_F64) for (d, r, _, _) in small)
+    res = serve(big + small, workers=3, hbm_budget=fb + fs)
+    b0, b1 = res[0], res[1]
+    assert b1["t_start"] >= b0["t_done"] - 1e-6          # the budget holds one large request
+    sm = res[2:]
+    assert all(c["status"] == 0 and c["batched"] for c in sm)
+    assert max(c["batch_size"] for c in sm) > 1
+    assert max(c["t_done"] for c in sm) <= b1["t_start"] + 1e-6
+    cfg = tt.batch_default_config()
+    for (dims, r_max, tol, X), c in zip(small, sm):
+        same(c["result"], tt.ttsvd_decompose_batch([X], [dims], r_max, tol, cfg=cfg)[0])
