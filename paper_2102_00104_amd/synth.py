@@ -154,9 +154,49 @@ def exact_tt_device(dims: Sequence[int], ranks: Sequence[int], seed: int, noise:
     if noise > 0:
         g = torch.Generator(device=device)
         g.manual_seed(int(noise_seed))
-        scale = noise * float(torch.sqrt(torch.mean(X * X)))
+        # the scale stays a device scalar: no host synchronisation, so a
+        # producer can enqueue several tensors ahead of their use
+        scale = noise * torch.sqrt(torch.mean(X * X))
         X = X + scale * torch.randn(X.numel(), generator=g, device=device, dtype=X.dtype)
     return X if dtype is None else X.to(dtype)
+
+
+def serving_cores_device(dims: Sequence[int], ranks: Sequence[int], seed: int, device):
+    """The cores of ``exact_tt_device`` (unit variance, ``default_rng(seed)``)
+    as FP32 device matrices for ``serving_tensor``: the first as the row-major
+    (r_1, n_1) tensor, core k as (row-major (n_k r_k, r_{k-1}) tensor, r_k).
+    Building them ahead keeps host work and host-to-device copies out of a
+    replay loop."""
+    import torch
+    cores = gaussian_cores(dims, ranks, seed, unit_variance=True)
+    first = torch.from_numpy(np.ascontiguousarray(cores[0][0].T)).to(device, torch.float32)
+    rest = []
+    for G in cores[1:]:
+        r0, n, r1 = G.shape
+        Gt = torch.from_numpy(np.ascontiguousarray(G.reshape(r0, n * r1, order="F").T))
+        rest.append((Gt.to(device, torch.float32), int(r1)))
+    return first, rest
+
+
+def serving_tensor(cores_dev, noise: float, noise_seed: int, device):
+    """FP32 serving request tensor: the TT of ``cores_dev`` (from
+    ``serving_cores_device``) contracted in FP32 on the device, plus i.i.d.
+    Gaussian noise of `noise` times its RMS drawn by an FP32 device generator
+    seeded with noise_seed.  Nothing synchronises with the host, so a
+    producer can enqueue tensors ahead of their arrival.  Returns the flat
+    Fortran-ordered tensor."""
+    import torch
+    first, rest = cores_dev
+    T = first
+    for Gt, r1 in rest:
+        T = (Gt @ T).reshape(r1, -1)
+    X = T.reshape(-1)
+    if noise > 0:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(noise_seed))
+        scale = noise * torch.sqrt(torch.mean(X * X))
+        X.addcmul_(torch.randn(X.numel(), generator=g, device=device, dtype=X.dtype), scale)
+    return X
 
 
 def serving_trace(duration_s: float = 10.0, rate: float = 200.0, seed: int = 4,
