@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libttsvd.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "tsqr.hip", "tsmm.hip", "svd.hip", "batch.hip", "server.hip", "thick.hip",
+SOURCES = ["api.hip", "tsqr.hip", "tsqr_blk.hip", "tsmm.hip", "svd.hip", "batch.hip", "server.hip", "thick.hip",
            "profile.hip", "noalloc.hip", "machine.hip",
            "alg1.hip", "twosided.hip"]
 ARCH = os.environ.get("TTSVD_OFFLOAD_ARCH", "gfx950")

@@ -247,6 +247,52 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+// Reduce-scatter of N values per lane over the 64 lanes of a wave (the first
+// half of wave_allreduce_vec below, kept separate so that the cooperative
+// TSQR bodies compile exactly as before), by recursive halving (lane bit 5 keeps the upper half of the list at the first
+// stage, bit 4 at the second, ...) and a butterfly over the remaining lane
+// bits.  Returns, in every lane, the full sum of value number
+// lane >> (6 - log2(cpow2(N))) (zero for numbers >= N).
+template <int N, typename T>
+__device__ __forceinline__ T wave_reduce_keys(const T (&p)[N]) {
+    constexpr int NP = cpow2(N);
+    constexpr int Q = clog2(NP);
+    static_assert(NP <= kWave, "at most 64 values");
+    const int lane = lane_id();
+    T b[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) b[i] = (i < N) ? p[i] : T(0);
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+        const int d = 32 >> t;
+        const int half = NP >> (t + 1);
+        const bool hi = (lane & d) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            if (t == 0) {
+                b[i] = swap_add<32>(b[i], b[half + i]);
+            } else if (t == 1) {
+                b[i] = swap_add<16>(b[i], b[half + i]);
+            } else {
+                T send = hi ? b[i] : b[half + i];
+                T keep = hi ? b[half + i] : b[i];
+                if (t == 2) send = partner<8>(send);
+                else if (t == 3) send = partner<4>(send);
+                else if (t == 4) send = partner<2>(send);
+                else send = partner<1>(send);
+                b[i] = keep + send;
+            }
+        }
+    }
+    if (Q <= 0) b[0] = butterfly_add<32>(b[0]);
+    if (Q <= 1) b[0] = butterfly_add<16>(b[0]);
+    if (Q <= 2) b[0] = butterfly_add<8>(b[0]);
+    if (Q <= 3) b[0] = butterfly_add<4>(b[0]);
+    if (Q <= 4) b[0] = butterfly_add<2>(b[0]);
+    if (Q <= 5) b[0] = butterfly_add<1>(b[0]);
+    return b[0];
+}
+
 // All-reduce of N values per lane over the 64 lanes of a wave.  On return
 // every lane holds the N sums in p[].  Reduce-scatter by recursive halving
 // (lane bit 5 keeps the upper half of the list at the first stage, bit 4 at

@@ -18,6 +18,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
+#include "tsqr_blk.h"
 #include "tsqr_dev.h"
 
 namespace ttsvd {
@@ -194,7 +195,7 @@ constexpr int64_t kMaxColsSlices = 256;   // 1024-thread slices: 1 per CU
 constexpr int cols_rows_per_lane(int g) { return g == 1 ? 32 : 16; }
 
 // Kernel family and shape for m columns.
-enum class Kind { Rows, Coop, Cols };
+enum class Kind { Rows, Coop, Blk, Cols };
 struct Shape {
     Kind kind;
     int M;       // column bucket (Rows, Coop)
@@ -230,6 +231,16 @@ CoopCfg coop_cfg(int M) {
     return M == 16 ? kCoop16[v] : M == 32 ? kCoop32[v] : M == 64 ? kCoop64[v] : kCoop128[v];
 }
 
+// TTSVD_TSQR_BLK=0 selects the column-group kernel for 128 < m <= 512 instead
+// of the blocked one (a tuning override).
+bool blk_enabled() {
+    static bool v = [] {
+        const char *e = getenv("TTSVD_TSQR_BLK");
+        return !(e && atoi(e) == 0);
+    }();
+    return v;
+}
+
 Shape shape_for(int64_t m) {
     Shape sh{Kind::Cols, 0, 0, 0, 0, 0};
     if (m <= 8) {
@@ -244,6 +255,9 @@ Shape shape_for(int64_t m) {
         sh.nw = c.nw;
         sh.rpt = c.rpt;
         sh.tile = (int64_t)kWave * sh.rpt;
+    } else if (m <= kBlkMaxM && blk_enabled()) {
+        sh.kind = Kind::Blk;
+        sh.tile = kBlkTR;
     } else {
         sh.g = m <= 256 ? 4 : m <= 512 ? 2 : 1;
         sh.tile = (int64_t)sh.g * cols_rows_per_lane(sh.g);
@@ -268,6 +282,18 @@ int64_t min_tiles() {
 
 std::vector<Level> plan(int64_t rows, int64_t m) {
     const Shape sh = shape_for(m);
+    if (sh.kind == Kind::Blk) {
+        // one tile per slice; every level stacks the tiles' factors
+        std::vector<Level> lv;
+        int64_t r = rows;
+        for (;;) {
+            const int64_t ns = std::max<int64_t>(1, ceil_div(r, sh.tile));
+            lv.push_back(Level{r, ns, sh.tile});
+            if (ns == 1 || (int)lv.size() == kTsqrMaxLevels) break;
+            r = ns * m;
+        }
+        return lv;
+    }
     TsqrPlanParams pp;
     if (sh.kind == Kind::Rows)
         pp = {kMaxWaveSlices, min_tiles()};
@@ -293,7 +319,7 @@ void level_buffers(const std::vector<Level> &lv, int64_t m, size_t buf[2]) {
 template <typename Tin>
 int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level &l,
                      double *out, int64_t ld_out, int64_t out_stride, int kvalid,
-                     double *rws, hipStream_t s);
+                     double *rws, bool tree, hipStream_t s);
 
 template <typename Tin> const char *tname();
 template <> const char *tname<double>() { return "double"; }
@@ -303,7 +329,7 @@ template <> const char *tname<bf16>() { return "ttsvd::bf16"; }
 template <typename Tin>
 int launch_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level &l,
                  double *out, int64_t ld_out, int64_t out_stride, int kvalid,
-                 double *rws, hipStream_t s) {
+                 double *rws, bool tree, hipStream_t s) {
     char name[96];
     const Shape sh = shape_for(m);
     if (sh.kind == Kind::Rows)
@@ -311,10 +337,12 @@ int launch_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level 
     else if (sh.kind == Kind::Coop)
         snprintf(name, sizeof(name), "tsqr_coop_kernel<%d, %d, %d, %s>", sh.M, sh.nw, sh.rpt,
                  tname<Tin>());
+    else if (sh.kind == Kind::Blk)
+        snprintf(name, sizeof(name), "tsqr_blk_kernel<%s>", tname<Tin>());
     else
         snprintf(name, sizeof(name), "tsqr_cols_kernel<%d, %d, %s>", sh.g, cols_rows_per_lane(sh.g), tname<Tin>());
     prof_begin(s, name, (double)rows * (double)m * sizeof(Tin), 2.0 * (double)rows * (double)m * (double)m);
-    int rc = launch_level_raw(W, rows, m, ld, l, out, ld_out, out_stride, kvalid, rws, s);
+    int rc = launch_level_raw(W, rows, m, ld, l, out, ld_out, out_stride, kvalid, rws, tree, s);
     prof_end(s);
     return rc;
 }
@@ -322,7 +350,7 @@ int launch_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level 
 template <typename Tin>
 int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level &l,
                      double *out, int64_t ld_out, int64_t out_stride, int kvalid,
-                     double *rws, hipStream_t s) {
+                     double *rws, bool tree, hipStream_t s) {
     const Shape sh = shape_for(m);
     if (sh.kind == Kind::Rows) {
         dim3 grid((unsigned)ceil_div(l.nslices, kRowsWaves)), block(kRowsWaves * kWave);
@@ -365,6 +393,9 @@ int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Le
         }
 #undef TTSVD_COOP_LAUNCH
 #undef TTSVD_COOP_CASE
+    } else if (sh.kind == Kind::Blk) {
+        return tsqr_blk_level(W, rows, m, ld, tree, l.nslices, rws, out, ld_out, out_stride,
+                              kvalid, s);
     } else {
         dim3 grid((unsigned)l.nslices), block(kColsThreads);
 #define TTSVD_COLS_CASE(GG)                                                                   \
@@ -393,7 +424,9 @@ size_t tsqr_workspace_bytes(int dtype, int64_t rows, int64_t m) {
     std::vector<Level> lv = plan(rows, m);
     size_t buf[2] = {0, 0}, rws = 0;
     level_buffers(lv, m, buf);
-    if (m > 128)
+    if (shape_for(m).kind == Kind::Blk)
+        for (const Level &l : lv) rws = std::max(rws, (size_t)(blk_grid(l.nslices) * blk_region_doubles(m)));
+    else if (m > 128)
         for (const Level &l : lv) rws = std::max(rws, (size_t)(l.nslices * m) * (size_t)m);
     return (buf[0] + buf[1] + rws) * sizeof(double) + 256;
 }
@@ -421,19 +454,19 @@ int tsqr_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, d
         if (i == 0) {
             switch (dtype) {
                 case TTSVD_F64:
-                    rc = launch_level((const double *)W, rows, m, ld, l, out, ld_out, m, kv, rws, s);
+                    rc = launch_level((const double *)W, rows, m, ld, l, out, ld_out, m, kv, rws, false, s);
                     break;
                 case TTSVD_F32:
-                    rc = launch_level((const float *)W, rows, m, ld, l, out, ld_out, m, kv, rws, s);
+                    rc = launch_level((const float *)W, rows, m, ld, l, out, ld_out, m, kv, rws, false, s);
                     break;
                 case TTSVD_BF16:
-                    rc = launch_level((const bf16 *)W, rows, m, ld, l, out, ld_out, m, kv, rws, s);
+                    rc = launch_level((const bf16 *)W, rows, m, ld, l, out, ld_out, m, kv, rws, false, s);
                     break;
                 default:
                     return set_error(TTSVD_EUNSUPPORTED, "tsqr: dtype %d", dtype);
             }
         } else {
-            rc = launch_level(in, l.rows, m, l.rows, l, out, ld_out, m, kv, rws, s);
+            rc = launch_level(in, l.rows, m, l.rows, l, out, ld_out, m, kv, rws, true, s);
         }
         if (rc != TTSVD_OK) return rc;
         in = out;

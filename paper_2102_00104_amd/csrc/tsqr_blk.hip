@@ -1,0 +1,330 @@
+// Blocked Householder TSQR for 128 < m <= 512 columns (the Q-less TSQR of
+// Sec. 3.2 of arXiv 2102.00104 with the Householder step of Algorithm 6),
+// with the trailing updates on FP64 MFMA.
+//
+// A workgroup reduces one row tile of kBlkTR = 1024 rows at a time.  The tile
+// is copied (widened to FP64, zero padded) into a workspace region of the
+// workgroup, in a "row-quad" layout: element (r, c) at ((r/4) ldq + c) 4 +
+// r mod 4, ldq = m rounded up to 16, so that every MFMA operand load below
+// reads whole 128-byte lines.  Tiles are independent: each yields the m x m
+// factor of its rows, the factors are stacked and the next level reduces
+// them the same way until one tile remains.  At those tree levels a row block
+// of a stacked triangle whose index in its triangle exceeds the current panel
+// (and that is no pivot row) is still zero in the panel's columns; it is
+// skipped (its reflector entries are zero, so skipping changes nothing).
+//
+// Per 16-column panel p:
+//  * unblocked panel factorization: 16 Householder steps (Algorithm 6) on
+//    rows >= p of the panel; lane l of wave w holds rows 128 w + l + 64 i
+//    (i < 2) of the 16 panel columns, norms and dot products are reduced
+//    across the wave and then across the 8 waves through LDS;
+//  * compact WY form: H_p ... H_{p+15} = I - Y T Y^T with T upper triangular
+//    and unit diagonal (every reflector has ||v||^2 = 2), T built column by
+//    column from dot products of the same reductions;
+//  * trailing update C <- C - Y T^T Y^T C for the columns right of the panel,
+//    16 at a time, with v_mfma_f64_16x16x4f64: W = Y^T C per wave over its
+//    rows, summed across the waves through LDS, W' = T^T W, then C -= Y W'
+//    block by block of 16 rows.  Each wave updates only its own rows, so the
+//    tile needs no barrier beyond the one per 16 columns for W.
+#include <float.h>
+#include <stdio.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "tsqr_blk.h"
+
+namespace ttsvd {
+
+constexpr int kBlkWaves = 8;
+constexpr int kBlkThreads = kBlkWaves * kWave;
+constexpr int kBlkRW = kBlkTR / kBlkWaves;  // rows per wave
+constexpr int kBlkRPT = kBlkRW / kWave;     // rows per lane in the panel
+constexpr int kBlkKS = kBlkRW / 4;          // 4-row MFMA K-steps per wave
+constexpr int kBlkRB = kBlkRW / 16;         // 16-row MFMA row blocks per wave
+static_assert(kBlkRW % 16 == 0 && kBlkRPT >= 1, "tile shape");
+
+typedef double blk_d4 __attribute__((ext_vector_type(4)));
+
+struct BlkShared {
+    double y[kBlkTR * 16];              // reflectors of the panel, see yl()
+    double wpart[kBlkWaves][4][kWave];  // per-wave partial W, D layout
+    double red[2][kBlkWaves];           // per-wave partial column norms
+    double part[2][kBlkWaves][16];      // per-wave partial dot products
+    double u1[2];                       // pivot entry of the current column
+    double G[16][17];                   // G(k, j) = y_k . y_j, k < j
+    double tl[16][17];                  // T, row-major (padded)
+};
+
+// Offset of element (r, c) in a tile region (below 2^31: kBlkTR x 512 doubles).
+__device__ __forceinline__ int q4i(int r, int c, int ldq) {
+    return ((r >> 2) * ldq + c) * 4 + (r & 3);
+}
+
+// Position of Y(r, k) in LDS: row-major, 16 per row, k XOR-swizzled by
+// 2 ((r / 2) mod 8).  Both MFMA operand reads are then free of bank
+// conflicts: 4 rows x 16 reflectors (W = Y^T C) and 16 rows x 4 reflectors
+// (C -= Y W').
+__device__ __forceinline__ int yl(int r, int k) { return r * 16 + (k ^ (((r >> 1) & 7) << 1)); }
+
+template <typename Tin>
+__global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
+    const Tin *__restrict__ W, int64_t rows, int m, int64_t ld, int tri, int64_t ntiles,
+    double *__restrict__ ws, double *__restrict__ out, int64_t ld_out,
+    int64_t out_row0_stride, int kvalid) {
+    __shared__ BlkShared sh;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform (scalar)
+    const int lr = lane & 15, lg = lane >> 4;
+    const int ldq = (m + 15) & ~15;
+    const int rowb = w * kBlkRW;
+    double *tile = ws + (int64_t)blockIdx.x * blk_region_doubles(m);
+    const double eps = DBL_MIN;
+
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t r0 = t * kBlkTR;
+        const int nvalid = (int)min<int64_t>(kBlkTR, rows - r0);
+        // row r of the tile is row (r + rphase) mod tri of its stacked triangle
+        const int rphase = tri ? (int)(r0 % tri) : 0;
+        // copy-in: coalesced column reads, zero padding
+        for (int c = 0; c < ldq; ++c) {
+            const Tin *src = W + r0 + ld * (c < m ? c : 0);  // uniform
+#pragma unroll
+            for (int i = 0; i < kBlkTR / kBlkThreads; ++i) {
+                const int r = tid + kBlkThreads * i;
+                const bool ok = r < nvalid && c < m;
+                tile[q4i(r, c, ldq)] = ok ? (double)Elem<Tin>::load(src + r) : 0.0;
+            }
+        }
+        __syncthreads();
+
+        // panels beyond the valid rows only touch zero rows: skipped
+        const int npan = min(ldq, (nvalid + 15) & ~15) / 16;
+        for (int pi = 0; pi < npan; ++pi) {
+            const int p = pi * 16;
+            // ---------------------------------------- panel factorization
+            double a[kBlkRPT][16];
+            double dg[kBlkRPT];
+#pragma unroll
+            for (int i = 0; i < kBlkRPT; ++i) {
+                const int r = rowb + lane + kWave * i;
+                dg[i] = 0.0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) a[i][k] = tile[q4i(r, p + k, ldq)];
+            }
+            static_for<0, 16>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                constexpr int buf = j & 1;
+                const int dj = p + j;
+                // this lane's first row, opaque to the compiler in every step so
+                // that the row tests of all 16 steps are not hoisted together
+                int rl = rowb + lane;
+                __asm__ volatile("" : "+v"(rl));
+                // ||column j below the diagonal||^2 and the pivot u1
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < kBlkRPT; ++i) {
+                    const int r = rl + kWave * i;
+                    if (r > dj) s = fma(a[i][j], a[i][j], s);
+                    if (r == dj) sh.u1[buf] = a[i][j];
+                }
+                s = wave_sum(s);
+                if (lane == 0) sh.red[buf][w] = s;
+                __syncthreads();
+                double tot = 0.0;
+#pragma unroll
+                for (int q = 0; q < kBlkWaves; ++q) tot += sh.red[buf][q];
+                const double u1 = sh.u1[buf];
+                // Algorithm 6: t = ||u||^2 + eps, alpha = -sign(u1) sqrt(t + eps),
+                // v = (u - alpha e1) / sqrt(t - alpha u1), ||v||^2 = 2
+                tot = fma(u1, u1, tot);
+                double tt = tot + eps;
+                const double t2 = tt + eps;
+                double alpha = t2 * rsqrt_nr(t2);
+                alpha = (u1 > 0.0) ? -alpha : alpha;
+                tt = fma(-alpha, u1, tt);
+                const double beta = rsqrt_nr(tt);
+                double v[kBlkRPT];
+#pragma unroll
+                for (int i = 0; i < kBlkRPT; ++i) {
+                    const int r = rl + kWave * i;
+                    v[i] = r > dj ? beta * a[i][j] : (r == dj ? beta * (u1 - alpha) : 0.0);
+                    if (r == dj) dg[i] = alpha;
+                }
+                // v . (every other panel column): trailing columns k > j give
+                // the update coefficients, earlier reflectors k < j give
+                // G(k, j) = y_k . v (rows < dj of column k hold R entries, but
+                // v is zero there)
+                double d[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int i = 0; i < kBlkRPT; ++i) acc = fma(v[i], a[i][k], acc);
+                    d[k] = (k == j) ? 0.0 : acc;
+                }
+                const double dsum = wave_reduce_keys<16>(d);  // value lane >> 2
+                if ((lane & 3) == 0) sh.part[buf][w][lane >> 2] = dsum;
+                __syncthreads();
+                // lane k: value k summed over the waves in a fixed order
+                double gk = 0.0;
+                if (lane < 16) {
+#pragma unroll
+                    for (int q = 0; q < kBlkWaves; ++q) gk += sh.part[buf][q][lane];
+                    if (w == 0 && lane < j) sh.G[lane][j] = gk;
+                }
+#pragma unroll
+                for (int k = j + 1; k < 16; ++k) {
+                    const double g = read_lane(gk, k);
+#pragma unroll
+                    for (int i = 0; i < kBlkRPT; ++i) a[i][k] = fma(-g, v[i], a[i][k]);
+                }
+                // column j keeps R above the diagonal and the reflector from it down
+#pragma unroll
+                for (int i = 0; i < kBlkRPT; ++i)
+                    if (rl + kWave * i >= dj) a[i][j] = v[i];
+                __builtin_amdgcn_sched_barrier(0);  // keep the steps apart (register pressure)
+            });
+            // Y to LDS (zero above each reflector's first row); the panel's R rows
+#pragma unroll
+            for (int i = 0; i < kBlkRPT; ++i) {
+                const int r = rowb + lane + kWave * i;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    sh.y[yl(r, k)] = (r >= p + k) ? a[i][k] : 0.0;
+                    if (r >= p && r < p + 16)
+                        tile[q4i(r, p + k, ldq)] = (r < p + k) ? a[i][k] : (r == p + k ? dg[i] : 0.0);
+                }
+            }
+            // T: T(j, j) = 1, T(k, j) = -sum_{k <= q < j} T(k, q) G(q, j); lane k
+            // of wave 0 builds row k in LDS (G was written by wave 0 itself)
+            if (w == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane < 16) {
+                    for (int jj = 0; jj < 16; ++jj) {
+                        double tj = 0.0;
+                        for (int q = lane; q < jj; ++q) tj = fma(sh.tl[lane][q], sh.G[q][jj], tj);
+                        sh.tl[lane][jj] = (lane < jj) ? -tj : (lane == jj ? 1.0 : 0.0);
+                    }
+                }
+            }
+            __syncthreads();
+
+            // ---------------------------------------- trailing update
+            if (p + 16 < ldq) {
+                double tA[4];  // T^T(i, 4q + kk) = T(4q + kk, i), lane (i, kk) = (lr, lg)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tA[q] = sh.tl[4 * q + lg][lr];
+                // 16-row blocks of this wave that can hold nonzero reflector
+                // entries: rows >= p below the valid rows; in a stack of
+                // triangles, the pivot rows (< p + 16) and the rows whose index
+                // in their triangle is at most p + 15 (the others are untouched
+                // and zero in the panel's columns)
+                auto live = [&](int rb) {
+                    return rb + 15 >= p && rb < nvalid &&
+                           (tri == 0 || rb < p + 16 || ((rb + rphase) % tri) < p + 16);
+                };
+                for (int c0 = p + 16; c0 < ldq; c0 += 16) {
+                    // Lane parts of the addresses, made opaque to the compiler in
+                    // every chunk so that it recomputes the 64 per-block addresses
+                    // instead of keeping them all live across the loop.
+                    int lt = lr * 4 + lg;  // tile: C(rowb + 4 s + lg, c0 + lr)
+                    int la[4], lu[4];      // LDS: Y(rb + 4 u + lg, lr), Y(rb + lr, 4 u + lg)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        la[u] = yl(4 * u + lg, lr);
+                        lu[u] = yl(lr, 4 * u + lg);
+                    }
+                    __asm__ volatile("" : "+v"(lt));
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) __asm__ volatile("" : "+v"(la[u]), "+v"(lu[u]));
+                    // C(rowb + 4 s + lg, c0 + lr): B operand of W = Y^T C and,
+                    // four K-steps at a time, the accumulator of C -= Y W'
+                    double cv[kBlkKS];
+                    blk_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int b = 0; b < kBlkRB; ++b) {
+                        const int rb = rowb + 16 * b;
+                        if (live(rb)) {  // uniform
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                cv[4 * b + u] = tile[lt + (((rb >> 2) + u) * ldq + c0) * 4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const double ya = sh.y[la[u] + rb * 16];
+                                if (u & 1)
+                                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya, cv[4 * b + u], acc1, 0, 0, 0);
+                                else
+                                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya, cv[4 * b + u], acc0, 0, 0, 0);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sh.wpart[w][q][lane] = acc0[q] + acc1[q];
+                    __syncthreads();
+                    double wsum[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        double x = 0.0;
+#pragma unroll
+                        for (int u = 0; u < kBlkWaves; ++u) x += sh.wpart[u][q][lane];
+                        wsum[q] = x;
+                    }
+                    __syncthreads();  // wpart is rewritten by the next chunk
+                    // W' = T^T W (D layout: lane (lr, lg), value q = W'(4q + lg, c0 + lr))
+                    blk_d4 wp = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) wp = __builtin_amdgcn_mfma_f64_16x16x4f64(tA[q], wsum[q], wp, 0, 0, 0);
+                    // C(rows, cols) -= Y W', 16 rows at a time: D(i = row, j = col)
+                    // with rows rb + 4 u + lg in value u, A = -Y(rb + lr, 4q + lg),
+                    // B = W'(4q + lg, c0 + lr)
+#pragma unroll
+                    for (int b = 0; b < kBlkRB; ++b) {
+                        const int rb = rowb + 16 * b;
+                        if (live(rb)) {  // uniform
+                            blk_d4 D = {cv[4 * b], cv[4 * b + 1], cv[4 * b + 2], cv[4 * b + 3]};
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                D = __builtin_amdgcn_mfma_f64_16x16x4f64(-sh.y[lu[q] + rb * 16], wp[q], D, 0, 0, 0);
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) tile[lt + (((rb >> 2) + u) * ldq + c0) * 4] = D[u];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // the factor: rows 0..m-1 of the tile, upper triangle
+        for (int c = 0; c < m; ++c) {
+            double *dst = out + t * out_row0_stride + ld_out * c;  // uniform
+            for (int r = tid; r < m; r += kBlkThreads)
+                dst[r] = (r <= c && r < kvalid && r < nvalid) ? tile[q4i(r, c, ldq)] : 0.0;
+        }
+        __syncthreads();  // the next tile reuses the region
+    }
+}
+
+template <typename Tin>
+int tsqr_blk_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, bool tree, int64_t ntiles,
+                   double *ws, double *out, int64_t ld_out, int64_t out_stride, int kvalid,
+                   hipStream_t s) {
+    if (m <= 0 || m > kBlkMaxM) return set_error(TTSVD_EUNSUPPORTED, "tsqr_blk: m = %lld", (long long)m);
+    const int tri = (tree && m % 16 == 0) ? (int)m : 0;
+    const unsigned grid = (unsigned)blk_grid(ntiles);
+    hipLaunchKernelGGL((tsqr_blk_kernel<Tin>), dim3(grid), dim3(kBlkThreads), 0, s, W, rows, (int)m,
+                       ld, tri, ntiles, ws, out, ld_out, out_stride, kvalid);
+    TTSVD_HIP_TRY(hipGetLastError());
+    return TTSVD_OK;
+}
+
+template int tsqr_blk_level<double>(const double *, int64_t, int64_t, int64_t, bool, int64_t,
+                                    double *, double *, int64_t, int64_t, int, hipStream_t);
+template int tsqr_blk_level<float>(const float *, int64_t, int64_t, int64_t, bool, int64_t,
+                                   double *, double *, int64_t, int64_t, int, hipStream_t);
+template int tsqr_blk_level<bf16>(const bf16 *, int64_t, int64_t, int64_t, bool, int64_t,
+                                  double *, double *, int64_t, int64_t, int, hipStream_t);
+
+}  // namespace ttsvd

@@ -66,9 +66,14 @@ TSQR_SHAPES = [(1, 1), (5, 1), (1000, 1), (777, 2), (4096, 3), (5000, 4), (70001
                (12345, 8), (33333, 16), (20000, 13), (40000, 32), (30001, 31),
                (50000, 64), (9999, 33), (3000, 65), (4099, 100), (2500, 256),
                (600, 300), (10, 7), (3, 16), (17, 64), (40, 100),
-               # column-group kernel: several slices and tree levels with
-               # 4, 2 and 1 lanes per column
-               (20000, 200), (9000, 400), (5000, 520), (1100, 1000)]
+               # blocked kernel (128 < m <= 512, 1024-row tiles): several
+               # tiles and tree levels, ragged column counts, fewer rows than
+               # columns, a single ragged tile
+               (20000, 200), (9000, 400), (3000, 129), (2048, 512), (5000, 511),
+               (1025, 160), (100, 300), (700, 144),
+               # column-group kernel (m > 512): several slices and tree levels
+               # with 1 lane per column
+               (5000, 520), (1100, 1000)]
 
 
 @pytest.mark.parametrize("rows,cols", TSQR_SHAPES)

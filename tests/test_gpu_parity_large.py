@@ -44,9 +44,12 @@ def sign_rows(R):
 # (the planner caps the slice count; each slice then reduces several tiles
 # with its factor carried along): m = 2 and 8 (single-wave slices of
 # 512-row tiles, 2 and 3 tiles), m = 16, 32, 64 and 100 (cooperative
-# workgroups, 2 to 5 tiles).
+# workgroups, 2 to 5 tiles); m = 144 takes the blocked kernel.
 TSQR_TALL = [(1_200_000, 2), (3_000_000, 8), (600_000, 16), (1_000_000, 32),
-             (700_000, 64), (300_000, 100)]
+             (700_000, 64), (300_000, 100),
+             # blocked kernel: more 1024-row tiles than workgroups (each
+             # workgroup reduces several tiles in turn), three tree levels
+             (300_000, 144)]
 
 
 @pytest.mark.timeout(600)
