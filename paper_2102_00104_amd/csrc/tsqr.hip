@@ -425,7 +425,7 @@ size_t tsqr_workspace_bytes(int dtype, int64_t rows, int64_t m) {
     size_t buf[2] = {0, 0}, rws = 0;
     level_buffers(lv, m, buf);
     if (shape_for(m).kind == Kind::Blk)
-        for (const Level &l : lv) rws = std::max(rws, (size_t)(blk_grid(l.nslices) * blk_region_doubles(m)));
+        for (const Level &l : lv) rws = std::max(rws, (size_t)blk_ws_doubles(l.nslices, m));
     else if (m > 128)
         for (const Level &l : lv) rws = std::max(rws, (size_t)(l.nslices * m) * (size_t)m);
     return (buf[0] + buf[1] + rws) * sizeof(double) + 256;

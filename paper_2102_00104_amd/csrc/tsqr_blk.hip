@@ -32,6 +32,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "driver.h"
 #include "tsqr_blk.h"
 
 namespace ttsvd {
@@ -67,28 +68,63 @@ __device__ __forceinline__ int q4i(int r, int c, int ldq) {
 // (C -= Y W').
 __device__ __forceinline__ int yl(int r, int k) { return r * 16 + (k ^ (((r >> 1) & 7) << 1)); }
 
+// Wait until another workgroup has released flag (its writes before the
+// release become visible to every thread of this workgroup).  The wait is
+// bounded (20 s of the 100 MHz wall clock): the group is resident together by
+// construction, so the bound only guarantees that the launch always ends.
+constexpr uint64_t kBlkWaitTicks = 20ull * 100000000ull;
+__device__ __forceinline__ void blk_wait(int *flag) {
+    if (threadIdx.x == 0) {
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            if (wall_clock64() - t0 > kBlkWaitTicks) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Publish this workgroup's global writes so far and set flag.
+__device__ __forceinline__ void blk_release(int *flag) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// G workgroups share a tile (G > 1: one tile per group, launched
+// cooperatively so that the group is resident together): column chunk ci (16
+// columns) belongs to workgroup ci mod G, which copies it in, applies every
+// panel's update to it and writes its part of the factor.  All G factor each
+// panel redundantly (same arithmetic, same Y and T); the owner of chunk p+1
+// updates it first and releases flags[t * nch + p + 1], which the others wait
+// for before they load panel p+1.
 template <typename Tin>
 __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
     const Tin *__restrict__ W, int64_t rows, int m, int64_t ld, int tri, int64_t ntiles,
-    double *__restrict__ ws, double *__restrict__ out, int64_t ld_out,
-    int64_t out_row0_stride, int kvalid) {
+    int G, int *__restrict__ flags, double *__restrict__ ws, double *__restrict__ out,
+    int64_t ld_out, int64_t out_row0_stride, int kvalid) {
     __shared__ BlkShared sh;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform (scalar)
     const int lr = lane & 15, lg = lane >> 4;
     const int ldq = (m + 15) & ~15;
+    const int nch = ldq / 16;
     const int rowb = w * kBlkRW;
-    double *tile = ws + (int64_t)blockIdx.x * blk_region_doubles(m);
+    const int g = (int)(blockIdx.x % G);
+    const int64_t tg = blockIdx.x / G, ngroups = gridDim.x / G;
+    double *tile = ws + tg * blk_region_doubles(m);
     const double eps = DBL_MIN;
 
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int64_t t = tg; t < ntiles; t += ngroups) {
+        int *tflags = flags + t * nch;
         const int64_t r0 = t * kBlkTR;
         const int nvalid = (int)min<int64_t>(kBlkTR, rows - r0);
         // row r of the tile is row (r + rphase) mod tri of its stacked triangle
         const int rphase = tri ? (int)(r0 % tri) : 0;
-        // copy-in: coalesced column reads, zero padding
-        for (int c = 0; c < ldq; ++c) {
+        // copy-in of this workgroup's chunks: coalesced column reads, zero padding
+        for (int c = 16 * g; c < ldq; c += (c & 15) == 15 ? 16 * G - 15 : 1) {
             const Tin *src = W + r0 + ld * (c < m ? c : 0);  // uniform
 #pragma unroll
             for (int i = 0; i < kBlkTR / kBlkThreads; ++i) {
@@ -97,12 +133,15 @@ __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
                 tile[q4i(r, c, ldq)] = ok ? (double)Elem<Tin>::load(src + r) : 0.0;
             }
         }
+        if (G > 1 && g == 0) blk_release(&tflags[0]);
         __syncthreads();
 
         // panels beyond the valid rows only touch zero rows: skipped
         const int npan = min(ldq, (nvalid + 15) & ~15) / 16;
         for (int pi = 0; pi < npan; ++pi) {
             const int p = pi * 16;
+            const bool own_panel = (pi % G) == g;
+            if (G > 1 && !own_panel) blk_wait(&tflags[pi]);
             // ---------------------------------------- panel factorization
             double a[kBlkRPT][16];
             double dg[kBlkRPT];
@@ -186,15 +225,21 @@ __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
                     if (rl + kWave * i >= dj) a[i][j] = v[i];
                 __builtin_amdgcn_sched_barrier(0);  // keep the steps apart (register pressure)
             });
-            // Y to LDS (zero above each reflector's first row); the panel's R rows
+            // Y to LDS (zero above each reflector's first row); the owner writes
+            // the panel's diagonal block of the factor (rows p..p+15) directly
+            // to the output (the tile's panel columns may still be read by the
+            // other workgroups of the group)
+            double *odiag = out + t * out_row0_stride;
 #pragma unroll
             for (int i = 0; i < kBlkRPT; ++i) {
                 const int r = rowb + lane + kWave * i;
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     sh.y[yl(r, k)] = (r >= p + k) ? a[i][k] : 0.0;
-                    if (r >= p && r < p + 16)
-                        tile[q4i(r, p + k, ldq)] = (r < p + k) ? a[i][k] : (r == p + k ? dg[i] : 0.0);
+                    if (own_panel && r >= p && r < p + 16 && r < m && p + k < m) {
+                        const bool keep = r <= p + k && r < kvalid && r < nvalid;
+                        odiag[r + ld_out * (p + k)] = keep ? (r < p + k ? a[i][k] : dg[i]) : 0.0;
+                    }
                 }
             }
             // T: T(j, j) = 1, T(k, j) = -sum_{k <= q < j} T(k, q) G(q, j); lane k
@@ -227,7 +272,9 @@ __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
                     return rb + 15 >= p && rb < nvalid &&
                            (tri == 0 || rb < p + 16 || ((rb + rphase) % tri) < p + 16);
                 };
-                for (int c0 = p + 16; c0 < ldq; c0 += 16) {
+                // this workgroup's chunks, the next panel's first
+                const int c_first = p + 16 + 16 * ((g - (pi + 1) % G + G) % G);
+                for (int c0 = c_first; c0 < ldq; c0 += 16 * G) {
                     // Lane parts of the addresses, made opaque to the compiler in
                     // every chunk so that it recomputes the 64 per-block addresses
                     // instead of keeping them all live across the loop.
@@ -293,18 +340,30 @@ __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
                             for (int u = 0; u < 4; ++u) tile[lt + (((rb >> 2) + u) * ldq + c0) * 4] = D[u];
                         }
                     }
+                    if (G > 1 && c0 == p + 16) blk_release(&tflags[pi + 1]);
                 }
             }
             __syncthreads();
         }
-        // the factor: rows 0..m-1 of the tile, upper triangle
-        for (int c = 0; c < m; ++c) {
+        // this workgroup's columns of the factor: rows above the diagonal block
+        // from the tile, the diagonal block written with its panel (if that
+        // panel ran), zero below
+        for (int c = 16 * g; c < m; c += (c & 15) == 15 ? 16 * G - 15 : 1) {
             double *dst = out + t * out_row0_stride + ld_out * c;  // uniform
-            for (int r = tid; r < m; r += kBlkThreads)
-                dst[r] = (r <= c && r < kvalid && r < nvalid) ? tile[q4i(r, c, ldq)] : 0.0;
+            const int c16 = c & ~15;
+            for (int r = tid; r < m; r += kBlkThreads) {
+                if (r >= c16 && r < c16 + 16 && c16 < npan * 16) continue;
+                dst[r] = (r < c16 && r < kvalid && r < nvalid) ? tile[q4i(r, c, ldq)] : 0.0;
+            }
         }
         __syncthreads();  // the next tile reuses the region
     }
+}
+
+__global__ void blk_zero_flags(int *flags, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        flags[i] = 0;
 }
 
 template <typename Tin>
@@ -312,11 +371,30 @@ int tsqr_blk_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, bool tree,
                    double *ws, double *out, int64_t ld_out, int64_t out_stride, int kvalid,
                    hipStream_t s) {
     if (m <= 0 || m > kBlkMaxM) return set_error(TTSVD_EUNSUPPORTED, "tsqr_blk: m = %lld", (long long)m);
-    const int tri = (tree && m % 16 == 0) ? (int)m : 0;
-    const unsigned grid = (unsigned)blk_grid(ntiles);
-    hipLaunchKernelGGL((tsqr_blk_kernel<Tin>), dim3(grid), dim3(kBlkThreads), 0, s, W, rows, (int)m,
-                       ld, tri, ntiles, ws, out, ld_out, out_stride, kvalid);
+    int tri = (tree && m % 16 == 0) ? (int)m : 0;
+    int G = blk_group(ntiles, m);
+    const int64_t grid = blk_grid(ntiles, m);
+    const int64_t nflags = G > 1 ? ntiles * ((m + 15) / 16) : 0;
+    int *flags = reinterpret_cast<int *>(ws);
+    double *regions = ws + (G > 1 ? (nflags + 63) / 64 * 32 : 0);
+    int mi = (int)m;
+    if (G == 1) {
+        hipLaunchKernelGGL((tsqr_blk_kernel<Tin>), dim3((unsigned)grid), dim3(kBlkThreads), 0, s, W,
+                           rows, mi, ld, tri, ntiles, G, flags, regions, out, ld_out, out_stride,
+                           kvalid);
+        TTSVD_HIP_TRY(hipGetLastError());
+        return TTSVD_OK;
+    }
+    // a shared tile needs its G workgroups resident together: cooperative launch
+    hipLaunchKernelGGL(blk_zero_flags, dim3((unsigned)std::min<int64_t>(64, ceil_div(nflags, 256))),
+                       dim3(256), 0, s, flags, nflags);
     TTSVD_HIP_TRY(hipGetLastError());
+    void *args[] = {(void *)&W,     (void *)&rows,   (void *)&mi,  (void *)&ld,
+                    (void *)&tri,   (void *)&ntiles, (void *)&G,   (void *)&flags,
+                    (void *)&regions, (void *)&out,  (void *)&ld_out, (void *)&out_stride,
+                    (void *)&kvalid};
+    TTSVD_HIP_TRY(coop_launch((const void *)tsqr_blk_kernel<Tin>, dim3((unsigned)grid),
+                              dim3(kBlkThreads), args, 0, s));
     return TTSVD_OK;
 }
 
