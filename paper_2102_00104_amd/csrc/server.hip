@@ -27,6 +27,7 @@
 
 #include "common.h"
 #include "driver.h"
+#include "tsqr_blk.h"
 
 namespace ttsvd {
 namespace {
@@ -84,6 +85,8 @@ bool is_small(const std::vector<int64_t> &dims, int64_t r_max, int64_t max_elems
 
 void worker_main(ttsvd_server *S) {
     (void)hipSetDevice(S->device);
+    // several workers share the GPU: keep the TSQR launches non-cooperative
+    blk_shared_tiles() = false;
     hipStream_t st = nullptr;
     const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
     std::vector<Request> take;

@@ -17,11 +17,19 @@ __host__ __device__ inline int64_t blk_region_doubles(int64_t m) {
     return (int64_t)kBlkTR * ((m + 15) & ~int64_t(15));
 }
 
+// Shared tiles (G > 1) need a cooperative launch, which the library orders
+// after every earlier cooperative launch on the device.  A thread that runs
+// decompositions concurrently with others (the serving workers) turns them
+// off for its own calls, so that its TSQR levels stay ordinary launches that
+// overlap with the other streams' work.
+bool &blk_shared_tiles();
+
 // Workgroups per tile: up to 32 (one per 16-column chunk) while the tiles
 // times that fit one launch of kBlkMaxWG resident workgroups; 1 otherwise.
 inline int blk_group(int64_t ntiles, int64_t m) {
     const int64_t nch = (m + 15) / 16;
     int G = 1;
+    if (!blk_shared_tiles()) return 1;
     while (2 * G <= 32 && 2 * G <= nch && ntiles * 2 * G <= kBlkMaxWG) G *= 2;
     return G;
 }

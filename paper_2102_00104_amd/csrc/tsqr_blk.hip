@@ -360,6 +360,11 @@ __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
     }
 }
 
+bool &blk_shared_tiles() {
+    static thread_local bool on = true;
+    return on;
+}
+
 __global__ void blk_zero_flags(int *flags, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
