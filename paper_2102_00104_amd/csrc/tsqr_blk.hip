@@ -80,16 +80,22 @@ __device__ __forceinline__ void blk_wait(int *flag) {
             if (wall_clock64() - t0 > kBlkWaitTicks) break;
             __builtin_amdgcn_s_sleep(1);
         }
+        // one agent-scope acquire for the workgroup (the caches it
+        // invalidates are shared by all its waves)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-// Publish this workgroup's global writes so far and set flag.
+// Publish this workgroup's global writes so far and set flag: the barrier
+// orders every wave's stores before thread 0's agent-scope release, which
+// writes back the cache they sit in.
 __device__ __forceinline__ void blk_release(int *flag) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // G workgroups share a tile (G > 1: one tile per group, launched
@@ -249,11 +255,17 @@ __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 if (lane < 16) {
+                    // row `lane` of T in registers (T(lane, q) = 0 for q < lane)
+                    double tr[16];
+#pragma unroll
                     for (int jj = 0; jj < 16; ++jj) {
                         double tj = 0.0;
-                        for (int q = lane; q < jj; ++q) tj = fma(sh.tl[lane][q], sh.G[q][jj], tj);
-                        sh.tl[lane][jj] = (lane < jj) ? -tj : (lane == jj ? 1.0 : 0.0);
+#pragma unroll
+                        for (int q = 0; q < jj; ++q) tj = fma(tr[q], sh.G[q][jj], tj);
+                        tr[jj] = (lane < jj) ? -tj : (lane == jj ? 1.0 : 0.0);
                     }
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) sh.tl[lane][q] = tr[q];
                 }
             }
             __syncthreads();
