@@ -7,8 +7,6 @@
 
 #include <cmath>
 
-#include <hip/hip_cooperative_groups.h>
-
 #include "common.h"
 #include "driver.h"
 #include "kernels.h"
@@ -52,14 +50,48 @@ constexpr int kBlockMaxE = 16;  // elements per lane and vector
 struct BlockCtl {
     int big[kMaxSweeps];  // per sweep: workgroups that made a large rotation
     int sweeps;           // sweeps performed
+    unsigned count, gen;  // grid barrier: arrivals, completed barriers
 };
+
+// Zeroes the control block before a launch (an ordinary kernel, so the
+// sequence can be captured in a graph).
+__global__ void svd_block_ctl_zero(BlockCtl *ctl) {
+    int *p = reinterpret_cast<int *>(ctl);
+    for (int i = threadIdx.x; i < (int)(sizeof(BlockCtl) / sizeof(int)); i += blockDim.x) p[i] = 0;
+}
+
+// Grid barrier of the cooperative launch: one agent-scope atomic per
+// workgroup, the last arrival advances the generation.  The wait is bounded
+// (20 s of the 100 MHz wall clock; the grid is co-resident by construction,
+// so the bound only guarantees that the launch ends).
+__device__ __forceinline__ void svd_grid_sync(BlockCtl *ctl, unsigned &gen) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned target = gen + 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned prev =
+            __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+                if (wall_clock64() - t0 > 20ull * 100000000ull) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        gen = target;
+    }
+    __syncthreads();
+}
 
 template <int B, int NT>
 __global__ __launch_bounds__(NT) void svd_block_kernel(
     const double *__restrict__ R, int64_t ldr, int K, int m, int mp, int nb,
     double *__restrict__ A, BlockCtl *ctl) {
-    namespace cg = cooperative_groups;
-    cg::grid_group grid = cg::this_grid();
+    unsigned gen = 0;  // barriers passed (thread 0)
     constexpr int TPP = NT / B;  // lanes per pair
     static_assert(TPP <= kWave && (TPP & (TPP - 1)) == 0, "pair lanes inside one wave");
     extern __shared__ __attribute__((aligned(16))) double S[];  // 2B rows of mp
@@ -73,10 +105,9 @@ __global__ __launch_bounds__(NT) void svd_block_kernel(
         const int vv = (int)(idx / mp), e = (int)(idx % mp);
         A[idx] = (vv < K && e < m) ? R[vv + ldr * e] : 0.0;
     }
-    // One counter per sweep, zeroed before the first grid barrier and never
-    // reused, so every workgroup reads the same final count for its decision.
-    if (blockIdx.x == 0 && tid < kMaxSweeps) ctl->big[tid] = 0;
-    grid.sync();
+    // One counter per sweep (zeroed before the launch) and never reused, so
+    // every workgroup reads the same final count for its decision.
+    svd_grid_sync(ctl, gen);
 
     const int pi = tid / TPP;
     const int sub = tid % TPP;
@@ -153,12 +184,12 @@ __global__ __launch_bounds__(NT) void svd_block_kernel(
                 A[(int64_t)(bp * B + vv) * mp + e] = S[vv * mp + e];
                 A[(int64_t)(bq * B + vv) * mp + e] = S[(B + vv) * mp + e];
             }
-            grid.sync();
+            svd_grid_sync(ctl, gen);
         }
         if (big) big_wg = 1;
         __syncthreads();
         if (tid == 0 && big_wg) atomicAdd(&ctl->big[sweep], 1);
-        grid.sync();
+        svd_grid_sync(ctl, gen);
         const int nbig = __atomic_load_n(&ctl->big[sweep], __ATOMIC_RELAXED);
         if (nbig == 0) {
             ++sweep;
@@ -295,8 +326,9 @@ int svd_launch(const double *R, int64_t ldr, int64_t K, int64_t m, double *sigma
              : b.B == 16 ? (const void *)svd_block_kernel<16, kBlockThreads>
              : b.B == 8  ? (const void *)svd_block_kernel<8, kBlockThreads>
                          : (const void *)svd_block_kernel<4, kBlockThreads>;
-    hipError_t e = hipSuccess;
-    if (lds > 64 * 1024)
+    hipLaunchKernelGGL(svd_block_ctl_zero, dim3(1), dim3(64), 0, s, ctl);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && lds > 64 * 1024)
         e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess) e = coop_launch(fn, dim3(nbk), dim3(b.nt), args, lds, s);
     prof_end(s);
