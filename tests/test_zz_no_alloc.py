@@ -64,6 +64,21 @@ def test_noalloc_matches_workspace_form_two_calls(dtype_name):
         assert np.all(np.tril(b, -1) == 0)
 
 
+def test_noalloc_blocked_kernel_two_calls():
+    # 128 < m <= 512 takes the blocked TSQR, whose tile regions (and the
+    # flags of tiles shared by several workgroups) then live in the scratch:
+    # 20,000 x 200 (20 tiles, three levels), then a smaller 3,000 x 144
+    for rows, cols, seed in ((20_000, 200, 3), (3_000, 144, 4)):
+        log("noalloc blocked %dx%d" % (rows, cols))
+        ld = rows + 1
+        W = np.zeros((ld, cols))
+        W[:rows] = np.random.default_rng(seed).standard_normal((rows, cols))
+        a, b = both(W, rows, cols, ld, tt.TTSVD_F64, torch.float64)
+        assert np.array_equal(a, b), np.max(np.abs(a - b))
+        G = W[:rows].T @ W[:rows]
+        assert np.max(np.abs(b.T @ b - G)) <= 1e-12 * np.linalg.norm(W[:rows]) ** 2
+
+
 def test_noalloc_rejects_shapes_beyond_the_scratch():
     rows, cols = 1 << 20, 256
     assert tt.ttsvd_tsqr_workspace_size(tt.TTSVD_F64, rows, cols) > tt.NOALLOC_SCRATCH_BYTES
