@@ -53,6 +53,7 @@ struct BlkShared {
     double red[2][kBlkWaves];           // per-wave partial column norms
     double part[2][kBlkWaves][16];      // per-wave partial dot products
     double u1[2];                       // pivot entry of the current column
+    double nx[2][4];                    // next column's pivot rows before the update
     double G[16][17];                   // G(k, j) = y_k . y_j, k < j
     double tl[16][17];                  // T, row-major (padded)
 };
@@ -158,6 +159,10 @@ __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
 #pragma unroll
                 for (int k = 0; k < 16; ++k) a[i][k] = tile[q4i(r, p + k, ldq)];
             }
+            // ||u||^2 and the pivot of the next column, carried from one step to
+            // the next (see the end of a step); `direct` asks for a fresh sum
+            double nx_tot = 0.0, nx_u1 = 0.0;
+            bool nx_direct = true;
             static_for<0, 16>([&](auto jc) {
                 constexpr int j = decltype(jc)::value;
                 constexpr int buf = j & 1;
@@ -166,24 +171,27 @@ __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
                 // that the row tests of all 16 steps are not hoisted together
                 int rl = rowb + lane;
                 __asm__ volatile("" : "+v"(rl));
-                // ||column j below the diagonal||^2 and the pivot u1
-                double s = 0.0;
+                double tot = nx_tot, u1 = nx_u1;
+                if (nx_direct) {  // uniform
+                    // ||column j below the diagonal||^2 and the pivot u1
+                    double s = 0.0;
 #pragma unroll
-                for (int i = 0; i < kBlkRPT; ++i) {
-                    const int r = rl + kWave * i;
-                    if (r > dj) s = fma(a[i][j], a[i][j], s);
-                    if (r == dj) sh.u1[buf] = a[i][j];
+                    for (int i = 0; i < kBlkRPT; ++i) {
+                        const int r = rl + kWave * i;
+                        if (r > dj) s = fma(a[i][j], a[i][j], s);
+                        if (r == dj) sh.u1[buf] = a[i][j];
+                    }
+                    s = wave_sum(s);
+                    if (lane == 0) sh.red[buf][w] = s;
+                    __syncthreads();
+                    tot = 0.0;
+#pragma unroll
+                    for (int q = 0; q < kBlkWaves; ++q) tot += sh.red[buf][q];
+                    u1 = sh.u1[buf];
+                    tot = fma(u1, u1, tot);
                 }
-                s = wave_sum(s);
-                if (lane == 0) sh.red[buf][w] = s;
-                __syncthreads();
-                double tot = 0.0;
-#pragma unroll
-                for (int q = 0; q < kBlkWaves; ++q) tot += sh.red[buf][q];
-                const double u1 = sh.u1[buf];
                 // Algorithm 6: t = ||u||^2 + eps, alpha = -sign(u1) sqrt(t + eps),
                 // v = (u - alpha e1) / sqrt(t - alpha u1), ||v||^2 = 2
-                tot = fma(u1, u1, tot);
                 double tt = tot + eps;
                 const double t2 = tt + eps;
                 double alpha = t2 * rsqrt_nr(t2);
@@ -201,13 +209,37 @@ __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
                 // the update coefficients, earlier reflectors k < j give
                 // G(k, j) = y_k . v (rows < dj of column k hold R entries, but
                 // v is zero there)
+                // Slot j carries N = ||column j+1 over rows >= dj||^2 before the
+                // update: the reflector preserves it, so the next step's
+                // ||u||^2 is N - R(dj, j+1)^2 without another reduction (the
+                // pivot rows dj and dj+1 of column j+1 and of v go through LDS).
                 double d[16];
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     double acc = 0.0;
+                    if (k != j) {
 #pragma unroll
-                    for (int i = 0; i < kBlkRPT; ++i) acc = fma(v[i], a[i][k], acc);
-                    d[k] = (k == j) ? 0.0 : acc;
+                        for (int i = 0; i < kBlkRPT; ++i) acc = fma(v[i], a[i][k], acc);
+                    } else if (j + 1 < 16) {
+#pragma unroll
+                        for (int i = 0; i < kBlkRPT; ++i)
+                            if (rl + kWave * i >= dj) acc = fma(a[i][j + 1], a[i][j + 1], acc);
+                    }
+                    d[k] = acc;
+                }
+                if (j + 1 < 16) {
+#pragma unroll
+                    for (int i = 0; i < kBlkRPT; ++i) {
+                        const int r = rl + kWave * i;
+                        if (r == dj) {
+                            sh.nx[buf][0] = a[i][(j + 1) & 15];
+                            sh.nx[buf][1] = v[i];
+                        }
+                        if (r == dj + 1) {
+                            sh.nx[buf][2] = a[i][(j + 1) & 15];
+                            sh.nx[buf][3] = v[i];
+                        }
+                    }
                 }
                 const double dsum = wave_reduce_keys<16>(d);  // value lane >> 2
                 if ((lane & 3) == 0) sh.part[buf][w][lane >> 2] = dsum;
@@ -229,6 +261,18 @@ __global__ __launch_bounds__(kBlkThreads) void tsqr_blk_kernel(
 #pragma unroll
                 for (int i = 0; i < kBlkRPT; ++i)
                     if (rl + kWave * i >= dj) a[i][j] = v[i];
+                // the next step's ||u||^2 and pivot, identical in every thread
+                // (the pivot is the value the update just left in its lane);
+                // where the downdate would cancel (the column nearly in the span
+                // of the earlier ones), the next step sums afresh
+                if (j + 1 < 16) {
+                    const double n2 = read_lane(gk, j);
+                    const double wn = read_lane(gk, (j + 1) & 15);
+                    const double rjn = fma(-wn, sh.nx[buf][1], sh.nx[buf][0]);
+                    nx_u1 = fma(-wn, sh.nx[buf][3], sh.nx[buf][2]);
+                    nx_tot = fma(-rjn, rjn, n2);
+                    nx_direct = !(nx_tot >= 0.25 * n2) || !(n2 > 0.0);
+                }
                 __builtin_amdgcn_sched_barrier(0);  // keep the steps apart (register pressure)
             });
             // Y to LDS (zero above each reflector's first row); the owner writes

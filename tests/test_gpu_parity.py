@@ -103,6 +103,23 @@ def test_tsqr_rank_deficient_and_zero_columns():
     assert np.max(np.abs(Rg.T @ Rg - G)) <= 1e-12 * np.linalg.norm(W) ** 2
 
 
+@pytest.mark.parametrize("rows,cols,rank", [(5000, 300, 8), (3000, 144, 100), (2500, 256, 250)])
+def test_tsqr_rank_deficient_blocked(rows, cols, rank):
+    # the blocked kernel (128 < m <= 512) on rank-deficient input with a zero
+    # column: the column norms it carries from one Householder step to the
+    # next cancel there and must be recomputed
+    rng = np.random.default_rng(rows + cols)
+    W = rng.standard_normal((rows, rank)) @ rng.standard_normal((rank, cols))
+    W[:, cols // 3] = 0.0
+    Rg = gpu_tsqr(W)
+    s = np.linalg.svd(Rg, compute_uv=False)
+    s_true = np.linalg.svd(W, compute_uv=False)
+    assert np.max(np.abs(s[:rank] - s_true[:rank])) <= 1e-12 * s_true[0]
+    assert s[rank] < 1e-13 * s[0]
+    G = W.T @ W
+    assert np.max(np.abs(Rg.T @ Rg - G)) <= 1e-12 * np.linalg.norm(W) ** 2
+
+
 def test_tsqr_deterministic():
     W = np.random.default_rng(22).random((100000, 16))
     a = gpu_tsqr(W)
