@@ -481,12 +481,17 @@ static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int
             const int64_t m = dims[i] * ranks[i + 1];
             const int64_t rows = nb / m;
             const int64_t K = std::min(rows, m);
-            // R from the QR decomposition of W^(i)
-            TTSVD_STEP_TRY(tsqr_launch(Wcur, dt, rows, m, ld, Rbuf, m, tq, f.tsqr_ws, s));
+            // R from the QR decomposition of W^(i).  A wide FP64 unfolding
+            // (rows <= m) goes to the SVD as it is: its rows have the singular
+            // values and right singular vectors of R, and the Jacobi SVD
+            // orthogonalises rows, so the QR would only add a launch.
+            const bool wide = dt == TTSVD_F64 && rows <= m;
+            if (!wide) TTSVD_STEP_TRY(tsqr_launch(Wcur, dt, rows, m, ld, Rbuf, m, tq, f.tsqr_ws, s));
             // small SVD, rank, core T^(i)
-            TTSVD_STEP_TRY(svd_launch(Rbuf, m, K, m, sig_dev + f.sigma_off[i], out->cores[i],
-                                      r_max, tol, d - 1, i == d - 1, &state->step[i],
-                                      &state->step[d - 1], sv, f.svd_ws, s));
+            TTSVD_STEP_TRY(svd_launch(wide ? (const double *)Wcur : Rbuf, wide ? ld : m, K, m,
+                                      sig_dev + f.sigma_off[i], out->cores[i], r_max, tol, d - 1,
+                                      i == d - 1, &state->step[i], &state->step[d - 1], sv,
+                                      f.svd_ws, s));
             int64_t r;
             if (tol == 0.0) {
                 r = std::min(r_max, K);

@@ -129,7 +129,10 @@ __device__ void svd_epilogue(ARef A, int lda, int K, int m, double *sig, int *or
     for (int64_t idx = tid; idx < r * m; idx += nth) {
         const int a = (int)(idx % r), c = (int)(idx / r);
         const int v = order[a];
-        core_out[idx] = A[(int64_t)v * lda + c] / sig[v];
+        // an exactly zero row (possible only for an unfolding passed without
+        // its QR) has no direction: its core row is zero
+        const double sv = sig[v];
+        core_out[idx] = sv > 0.0 ? A[(int64_t)v * lda + c] / sv : 0.0;
     }
     // the caller may reuse sig / order / A after this point
     __syncthreads();
