@@ -377,6 +377,16 @@ void ttsvd_tt_free(ttsvd_tt *tt) {
     memset(tt, 0, sizeof(*tt));
 }
 
+// TTSVD_TSMM_QR=0 keeps the product and the next step's first TSQR level as
+// separate launches (a tuning override; the results are the same).
+static bool tsmm_qr_enabled() {
+    static bool v = [] {
+        const char *e = getenv("TTSVD_TSMM_QR");
+        return !(e && atoi(e) == 0);
+    }();
+    return v;
+}
+
 static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int64_t r_max,
                           double tol, void *ws_in, size_t ws_bytes, double *cores_in,
                           size_t cores_doubles, ttsvd_tt *out) {
@@ -477,6 +487,7 @@ static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int
         int64_t ld = ld0;
         int64_t nb = nbar;
         int pp = 0;
+        int pre_levels = 0;  // levels of this step's TSQR done with the previous product
         for (int i = d - 1; i >= 1; --i) {
             const int64_t m = dims[i] * ranks[i + 1];
             const int64_t rows = nb / m;
@@ -486,7 +497,10 @@ static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int
             // values and right singular vectors of R, and the Jacobi SVD
             // orthogonalises rows, so the QR would only add a launch.
             const bool wide = dt == TTSVD_F64 && rows <= m;
-            if (!wide) TTSVD_STEP_TRY(tsqr_launch(Wcur, dt, rows, m, ld, Rbuf, m, tq, f.tsqr_ws, s));
+            if (pre_levels)  // level 0 came with the previous product
+                TTSVD_STEP_TRY(tsqr_launch_after_first(dt, rows, m, Rbuf, m, tq, f.tsqr_ws, s));
+            else if (!wide)
+                TTSVD_STEP_TRY(tsqr_launch(Wcur, dt, rows, m, ld, Rbuf, m, tq, f.tsqr_ws, s));
             // small SVD, rank, core T^(i)
             TTSVD_STEP_TRY(svd_launch(wide ? (const double *)Wcur : Rbuf, wide ? ld : m, K, m,
                                       sig_dev + f.sigma_off[i], out->cores[i], r_max, tol, d - 1,
@@ -514,8 +528,13 @@ static int decompose_impl(const ttsvd_tensor *X, const int64_t *dims, int d, int
             void *Y = (i >= 2) ? wbuf[pp] : (void *)out->cores[0];
             const int ydt = (i >= 2) ? dt : TTSVD_F64;
             const int64_t ld_y = rows / n_next;
-            TTSVD_STEP_TRY(tsmm_launch(Wcur, dt, rows, m, ld, out->cores[i], r, 1, r, n_next, Y,
-                                       ydt, ld_y, s));
+            pre_levels = 0;
+            if (i >= 2 && tsmm_qr_enabled() && tsmm_qr_applies(dt, rows, m, r, n_next))
+                TTSVD_STEP_TRY(tsmm_qr_launch(Wcur, dt, rows, m, ld, out->cores[i], r, 1, r, n_next,
+                                              Y, Rbuf, n_next * r, tq, f.tsqr_ws, s, &pre_levels));
+            else
+                TTSVD_STEP_TRY(tsmm_launch(Wcur, dt, rows, m, ld, out->cores[i], r, 1, r, n_next, Y,
+                                           ydt, ld_y, s));
             Wcur = Y;
             ld = ld_y;
             nb = rows * r;

@@ -21,15 +21,19 @@ struct bf16 {
 };
 
 template <typename T> struct Elem;
+// load / store widen and narrow between the storage and accumulation types;
+// round(v) is the value that store(p, v) leaves for a later load(p).
 template <> struct Elem<double> {
     using acc = double;
     __device__ static inline double load(const double *p) { return *p; }
     __device__ static inline void store(double *p, double v) { *p = v; }
+    __device__ static inline double round(double v) { return v; }
 };
 template <> struct Elem<float> {
     using acc = float;
     __device__ static inline float load(const float *p) { return *p; }
     __device__ static inline void store(float *p, float v) { *p = v; }
+    __device__ static inline float round(float v) { return v; }
 };
 template <> struct Elem<bf16> {
     using acc = float;
@@ -46,6 +50,7 @@ template <> struct Elem<bf16> {
     __device__ static inline void store(bf16 *p, float v) {
         p->bits = static_cast<uint16_t>(bits(v));
     }
+    __device__ static inline float round(float v) { return __uint_as_float(bits(v) << 16); }
 };
 
 // *p widened to the accumulation type if ok, else zero.  p must be a valid

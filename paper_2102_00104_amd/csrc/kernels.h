@@ -15,6 +15,12 @@ int tsqr_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld,
                 double *R, int64_t ldr, void *ws, size_t ws_bytes,
                 hipStream_t s);
 
+// Levels 1.. of the TSQR of a rows x m unfolding whose level 0 was written by
+// tsmm_qr_launch into the same workspace (nothing to do if it was the only
+// level: R is then written already).
+int tsqr_launch_after_first(int dtype, int64_t rows, int64_t m, double *R, int64_t ldr,
+                            void *ws, size_t ws_bytes, hipStream_t s);
+
 // ---------------------------------------------------------------- TSMM
 // Y = reshape(W V, (rows/n_next, n_next k)), V(c, a) = V[c*svc + a*sva] (FP64).
 // W has element type dtype; Y has element type ydtype (equal to dtype, or
@@ -23,6 +29,20 @@ int tsmm_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld,
                 const double *V, int64_t svc, int64_t sva, int64_t k,
                 int64_t n_next, void *Y, int ydtype, int64_t ld_y,
                 hipStream_t s);
+
+// The product of tsmm_launch (ydtype = dtype, ld_y = rows / n_next) fused
+// with level 0 of the TSQR of Y, for the shapes tsmm_qr_applies accepts (W
+// with m <= 8 columns, n_next in {2, 4}, n_next k <= 8 and Y not wider than
+// tall): writes Y and level 0's factors (R itself, ldr, if that is the only
+// level; else the stacked factors at the start of ws, which holds
+// tsqr_workspace_bytes(dtype, rows / n_next, n_next k) bytes), and sets
+// *levels_done = 1.  Y and the factors equal those of tsmm_launch followed
+// by tsqr_launch.
+bool tsmm_qr_applies(int dtype, int64_t rows, int64_t m, int64_t k, int64_t n_next);
+int tsmm_qr_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld,
+                   const double *V, int64_t svc, int64_t sva, int64_t k, int64_t n_next, void *Y,
+                   double *R, int64_t ldr, void *ws, size_t ws_bytes, hipStream_t s,
+                   int *levels_done);
 
 // ---------------------------------------------------------------- SVD
 // Device state shared by the steps of one decomposition.

@@ -45,6 +45,74 @@ __global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
                                     out_row0_stride, kvalid, smem);
 }
 
+// Product and first TSQR level of the next unfolding in one pass (the TSMM of
+// Sec. 4.1.2 followed by the flat reduction of Sec. 3.2): for the next
+// unfolding Y = reshape(W V, (rows_n, NN k)) with NN k <= M <= 8 columns,
+// every wave builds its row tiles of Y from W and V (row y, column q + NN a of
+// Y is row y + q rows_n of W V, column a), stores them and reduces them in the
+// same registers, so Y is not read back for its QR.  The product accumulates
+// over the columns of W in ascending order exactly as the TSMM kernel does,
+// and the reduction is the rows body itself: Y and the factors equal those of
+// the separate launches bit for bit.  W has mp <= 8 columns, V is FP64
+// (V(c, a) = V[c svc + a sva]).
+template <int M, int NN, int RPT, typename Tin>
+__global__ __launch_bounds__(kRowsWaves *kWave) void tsmm_qr_kernel(
+    const Tin *__restrict__ W, int mp, int64_t ld, const double *__restrict__ V, int64_t svc,
+    int64_t sva, int k, Tin *__restrict__ Y, int64_t rows_n, int64_t rows_per_slice,
+    int64_t nslices, double *__restrict__ out, int64_t ld_out, int64_t out_row0_stride,
+    int kvalid) {
+    using T = typename Elem<Tin>::acc;
+    constexpr int KB = M / NN;  // columns of V per block of Y columns
+    static_assert(KB * NN == M, "NN must divide M");
+    __shared__ __attribute__((aligned(16))) char smem[tsqr_rows_smem<M, RPT, Tin>()];
+    __shared__ T vs[8][KB];
+    for (int idx = threadIdx.x; idx < 8 * KB; idx += blockDim.x) {
+        const int c = idx / KB, a = idx % KB;
+        vs[c][a] = (c < mp && a < k) ? (T)V[c * svc + a * sva] : T(0);
+    }
+    __syncthreads();
+    tsqr_rows_core<M, RPT, T, kRowsWaves>(
+        rows_n, NN * k, rows_per_slice, nslices, out, ld_out, out_row0_stride, kvalid,
+        blockIdx.x, smem, [&](int64_t base, int64_t r0, int64_t r1, T (&y)[RPT][M]) {
+            const int lane = lane_id();
+            int64_t rc[RPT];
+            bool ok[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int64_t row = base + lane + (int64_t)kWave * i;
+                ok[i] = row < r1;
+                rc[i] = ok[i] ? row : r0;
+            }
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < M; ++c) y[i][c] = T(0);
+            for (int c = 0; c < mp; ++c) {
+                T vv[KB];
+#pragma unroll
+                for (int a = 0; a < KB; ++a) vv[a] = vs[c][a];
+#pragma unroll
+                for (int q = 0; q < NN; ++q)
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) {
+                        const T w = load_or_zero(W + (rc[i] + q * rows_n) + ld * c, ok[i]);
+#pragma unroll
+                        for (int a = 0; a < KB; ++a) y[i][q + NN * a] = fma(w, vv[a], y[i][q + NN * a]);
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int q = 0; q < NN; ++q)
+#pragma unroll
+                    for (int a = 0; a < KB; ++a) {
+                        T &e = y[i][q + NN * a];
+                        e = Elem<Tin>::round(e);  // the value Y holds
+                        if (ok[i] && a < k) Elem<Tin>::store(Y + rc[i] + rows_n * (q + NN * a), e);
+                    }
+        });
+}
+
 // ----------------------------------------------------------------------------
 // Column-group workgroup kernel, 128 < m <= 1024 / G.
 //
@@ -431,8 +499,12 @@ size_t tsqr_workspace_bytes(int dtype, int64_t rows, int64_t m) {
     return (buf[0] + buf[1] + rws) * sizeof(double) + 256;
 }
 
-int tsqr_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, double *R,
-                int64_t ldr, void *ws, size_t ws_bytes, hipStream_t s) {
+namespace {
+
+// Levels from..end of the TSQR of W; levels before `from` have already
+// written their stacked factors where this function would have.
+int tsqr_levels(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, double *R,
+                int64_t ldr, void *ws, size_t ws_bytes, hipStream_t s, size_t from) {
     if (m > 1024) return set_error(TTSVD_EUNSUPPORTED, "tsqr: cols = %lld > 1024", (long long)m);
     std::vector<Level> lv = plan(rows, m);
     size_t buf[2] = {0, 0};
@@ -444,7 +516,8 @@ int tsqr_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, d
     double *rws = b1 + buf[1];
     const int kvalid = (int)std::min<int64_t>(rows, m);
     const double *in = nullptr;
-    for (size_t i = 0; i < lv.size(); ++i) {
+    if (from > 0 && from < lv.size()) in = ((from - 1) & 1) ? b1 : b0;
+    for (size_t i = from; i < lv.size(); ++i) {
         const Level &l = lv[i];
         const bool last = (i + 1 == lv.size());
         double *out = last ? R : ((i & 1) ? b1 : b0);
@@ -472,6 +545,96 @@ int tsqr_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, d
         in = out;
     }
     return TTSVD_OK;
+}
+
+}  // namespace
+
+int tsqr_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld, double *R,
+                int64_t ldr, void *ws, size_t ws_bytes, hipStream_t s) {
+    return tsqr_levels(W, dtype, rows, m, ld, R, ldr, ws, ws_bytes, s, 0);
+}
+
+int tsqr_launch_after_first(int dtype, int64_t rows, int64_t m, double *R, int64_t ldr,
+                            void *ws, size_t ws_bytes, hipStream_t s) {
+    return tsqr_levels(nullptr, dtype, rows, m, rows, R, ldr, ws, ws_bytes, s, 1);
+}
+
+bool tsmm_qr_applies(int dtype, int64_t rows, int64_t m, int64_t k, int64_t n_next) {
+    const int64_t mn = n_next * k;
+    return (dtype == TTSVD_F64 || dtype == TTSVD_F32 || dtype == TTSVD_BF16) && m >= 1 &&
+           m <= 8 && k >= 1 && (n_next == 2 || n_next == 4) && mn <= 8 && rows % n_next == 0 &&
+           rows / n_next > mn && shape_for(mn).kind == Kind::Rows;
+}
+
+template <typename Tin>
+static int tsmm_qr_typed(const Tin *W, int64_t rows, int64_t m, int64_t ld, const double *V,
+                         int64_t svc, int64_t sva, int64_t k, int64_t n_next, Tin *Y,
+                         const Level &l, double *out, int64_t ld_out, int kvalid, hipStream_t s) {
+    const int64_t rows_n = rows / n_next;
+    const int M = cpow2((int)(n_next * k));
+    dim3 grid((unsigned)ceil_div(l.nslices, kRowsWaves)), block(kRowsWaves * kWave);
+    char name[96];
+    snprintf(name, sizeof(name), "tsmm_qr_kernel<%d, %d, 8, %s>", M, (int)n_next, tname<Tin>());
+    prof_begin(s, name, (double)rows * (double)(m + k) * sizeof(Tin),
+               2.0 * (double)rows * (double)m * (double)k +
+                   2.0 * (double)rows_n * (double)(n_next * k) * (double)(n_next * k));
+#define TTSVD_TQ(MM, NN)                                                                         \
+    hipLaunchKernelGGL((tsmm_qr_kernel<MM, NN, 8, Tin>), grid, block, 0, s, W, (int)m, ld, V, svc, \
+                       sva, (int)k, Y, rows_n, l.rows_per_slice, l.nslices, out, ld_out,          \
+                       n_next * k, kvalid)
+    if (M == 2 && n_next == 2)
+        TTSVD_TQ(2, 2);
+    else if (M == 4 && n_next == 2)
+        TTSVD_TQ(4, 2);
+    else if (M == 4 && n_next == 4)
+        TTSVD_TQ(4, 4);
+    else if (M == 8 && n_next == 2)
+        TTSVD_TQ(8, 2);
+    else if (M == 8 && n_next == 4)
+        TTSVD_TQ(8, 4);
+    else {
+        prof_end(s);
+        return set_error(TTSVD_EUNSUPPORTED, "tsmm_qr: M = %d, n_next = %lld", M, (long long)n_next);
+    }
+#undef TTSVD_TQ
+    prof_end(s);
+    TTSVD_HIP_TRY(hipGetLastError());
+    return TTSVD_OK;
+}
+
+int tsmm_qr_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld,
+                   const double *V, int64_t svc, int64_t sva, int64_t k, int64_t n_next, void *Y,
+                   double *R, int64_t ldr, void *ws, size_t ws_bytes, hipStream_t s,
+                   int *levels_done) {
+    if (!tsmm_qr_applies(dtype, rows, m, k, n_next))
+        return set_error(TTSVD_EUNSUPPORTED, "tsmm_qr: shape");
+    const int64_t rows_n = rows / n_next, mn = n_next * k;
+    std::vector<Level> lv = plan(rows_n, mn);
+    size_t buf[2] = {0, 0};
+    level_buffers(lv, mn, buf);
+    if (ws_bytes < tsqr_workspace_bytes(dtype, rows_n, mn))
+        return set_error(TTSVD_EINVAL, "tsmm_qr: workspace too small");
+    const bool last = lv.size() == 1;
+    double *out = last ? R : (double *)ws;  // where level 0 of the TSQR of Y writes
+    const int64_t ld_out = last ? ldr : lv[0].nslices * mn;
+    const int kv = last ? (int)std::min<int64_t>(rows_n, mn) : (int)mn;
+    int rc;
+    switch (dtype) {
+        case TTSVD_F64:
+            rc = tsmm_qr_typed((const double *)W, rows, m, ld, V, svc, sva, k, n_next, (double *)Y,
+                               lv[0], out, ld_out, kv, s);
+            break;
+        case TTSVD_F32:
+            rc = tsmm_qr_typed((const float *)W, rows, m, ld, V, svc, sva, k, n_next, (float *)Y,
+                               lv[0], out, ld_out, kv, s);
+            break;
+        default:
+            rc = tsmm_qr_typed((const bf16 *)W, rows, m, ld, V, svc, sva, k, n_next, (bf16 *)Y,
+                               lv[0], out, ld_out, kv, s);
+            break;
+    }
+    if (rc == TTSVD_OK) *levels_done = 1;
+    return rc;
 }
 
 }  // namespace ttsvd

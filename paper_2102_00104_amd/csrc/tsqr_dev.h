@@ -34,12 +34,14 @@ constexpr size_t tsqr_rows_smem() {
     return sizeof(typename Elem<Tin>::acc) * WAVES * kWave;
 }
 
-template <int M, int RPT, typename Tin, int WAVES = kRowsWaves>
-__device__ __forceinline__ void tsqr_rows_body(
-    const Tin *__restrict__ W, int64_t rows, int m, int64_t ld, int64_t rows_per_slice,
-    int64_t nslices, double *__restrict__ out, int64_t ld_out, int64_t out_row0_stride,
-    int kvalid, int64_t vblock, void *smem) {
-    using T = typename Elem<Tin>::acc;
+// The body proper, with the row tile supplied by `load(base, r0, r1, a)`:
+// a[i][c] = element (base + lane + 64 i, c) of the slice [r0, r1), zero for
+// rows >= r1 and columns >= m.
+template <int M, int RPT, typename T, int WAVES, typename Load>
+__device__ __forceinline__ void tsqr_rows_core(
+    int64_t rows, int m, int64_t rows_per_slice, int64_t nslices, double *__restrict__ out,
+    int64_t ld_out, int64_t out_row0_stride, int kvalid, int64_t vblock, void *smem,
+    Load load) {
     constexpr int CH = (M < 16) ? M : 16;  // trailing columns per reduction
     const int lane = lane_id();
     const int wid = thread_id() / kWave;
@@ -56,15 +58,7 @@ __device__ __forceinline__ void tsqr_rows_body(
     T a[RPT][M];
 
     for (int64_t base = r0; base < r1; base += (int64_t)kWave * RPT) {
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const int64_t row = base + lane + (int64_t)kWave * i;
-            const bool ok = row < r1;
-            const int64_t rc = ok ? row : r0;
-#pragma unroll
-            for (int c = 0; c < M; ++c)
-                a[i][c] = load_or_zero(W + rc + ld * (c < m ? c : 0), ok && c < m);
-        }
+        load(base, r0, r1, a);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             if (j < m) {
@@ -125,6 +119,28 @@ __device__ __forceinline__ void tsqr_rows_body(
         for (int c = 0; c < M; ++c)
             if (c < m) out[orow + ld_out * c] = keep ? (double)R[c] : 0.0;
     }
+}
+
+template <int M, int RPT, typename Tin, int WAVES = kRowsWaves>
+__device__ __forceinline__ void tsqr_rows_body(
+    const Tin *__restrict__ W, int64_t rows, int m, int64_t ld, int64_t rows_per_slice,
+    int64_t nslices, double *__restrict__ out, int64_t ld_out, int64_t out_row0_stride,
+    int kvalid, int64_t vblock, void *smem) {
+    using T = typename Elem<Tin>::acc;
+    tsqr_rows_core<M, RPT, T, WAVES>(
+        rows, m, rows_per_slice, nslices, out, ld_out, out_row0_stride, kvalid, vblock, smem,
+        [&](int64_t base, int64_t r0, int64_t r1, T (&a)[RPT][M]) {
+            const int lane = lane_id();
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int64_t row = base + lane + (int64_t)kWave * i;
+                const bool ok = row < r1;
+                const int64_t rc = ok ? row : r0;
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+                    a[i][c] = load_or_zero(W + rc + ld * (c < m ? c : 0), ok && c < m);
+            }
+        });
 }
 
 // ----------------------------------------------------------------------------
