@@ -31,9 +31,9 @@ int tsmm_launch(const void *W, int dtype, int64_t rows, int64_t m, int64_t ld,
                 hipStream_t s);
 
 // The product of tsmm_launch (ydtype = dtype, ld_y = rows / n_next) fused
-// with level 0 of the TSQR of Y, for the shapes tsmm_qr_applies accepts (W
-// with m <= 8 columns, n_next in {2, 4}, n_next k <= 8 and Y not wider than
-// tall): writes Y and level 0's factors (R itself, ldr, if that is the only
+// with level 0 of the TSQR of Y, for the shapes tsmm_qr_applies accepts
+// (n_next in {2, 4}, Y taller than wide with n_next k <= 8 columns and W
+// with m <= 8, or n_next k <= 32 and m <= 32): writes Y and level 0's factors (R itself, ldr, if that is the only
 // level; else the stacked factors at the start of ws, which holds
 // tsqr_workspace_bytes(dtype, rows / n_next, n_next k) bytes), and sets
 // *levels_done = 1.  Y and the factors equal those of tsmm_launch followed

@@ -113,6 +113,71 @@ __global__ __launch_bounds__(kRowsWaves *kWave) void tsmm_qr_kernel(
         });
 }
 
+// The same fusion for a next unfolding of 8 < NN k <= M <= 32 columns, with
+// the cooperative body: wave w holds the columns NW kk + w of the tile, which
+// are q + NN a with q = w mod NN and a = (NW / NN) kk + w / NN (NN divides
+// NW), so a wave reads a single row block of W (rows y + q rows_n).  W has
+// mp <= kTqMaxMp columns.
+constexpr int kTqMaxMp = 32;
+
+template <int M, int NW, int RPT, int NN, typename Tin>
+__global__ __launch_bounds__(NW *kWave) void tsmm_qr_coop_kernel(
+    const Tin *__restrict__ W, int mp, int64_t ld, const double *__restrict__ V, int64_t svc,
+    int64_t sva, int k, Tin *__restrict__ Y, int64_t rows_n, int64_t rows_per_slice,
+    double *__restrict__ out, int64_t ld_out, int64_t out_row0_stride, int kvalid) {
+    using T = typename Elem<Tin>::acc;
+    constexpr int MW = M / NW;
+    constexpr int KB = M / NN;
+    static_assert(NW % NN == 0 && KB * NN == M, "NN must divide NW and M");
+    __shared__ __attribute__((aligned(16))) char smem[tsqr_coop_smem<M, NW, RPT, Tin>()];
+    __shared__ T vs[kTqMaxMp][KB];
+    for (int idx = threadIdx.x; idx < kTqMaxMp * KB; idx += blockDim.x) {
+        const int c = idx / KB, a = idx % KB;
+        vs[c][a] = (c < mp && a < k) ? (T)V[c * svc + a * sva] : T(0);
+    }
+    __syncthreads();
+    tsqr_coop_core<M, NW, RPT, T>(
+        rows_n, NN * k, rows_per_slice, blockIdx.x, out, ld_out, out_row0_stride, kvalid, smem,
+        [&](int64_t base, int64_t r0, int64_t r1, T (&y)[RPT][MW]) {
+            const int lane = lane_id();
+            const int w = thread_id() / kWave;
+            const int q = w % NN, a0 = w / NN;
+            int64_t rc[RPT];
+            bool ok[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int64_t row = base + lane + (int64_t)kWave * i;
+                ok[i] = row < r1;
+                rc[i] = (ok[i] ? row : r0) + q * rows_n;
+            }
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int kk = 0; kk < MW; ++kk) y[i][kk] = T(0);
+            for (int c = 0; c < mp; ++c) {
+                T vv[MW];
+#pragma unroll
+                for (int kk = 0; kk < MW; ++kk) vv[kk] = vs[c][(NW / NN) * kk + a0];
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const T x = load_or_zero(W + rc[i] + ld * c, ok[i]);
+#pragma unroll
+                    for (int kk = 0; kk < MW; ++kk) y[i][kk] = fma(x, vv[kk], y[i][kk]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int kk = 0; kk < MW; ++kk) {
+                    const int a = (NW / NN) * kk + a0;
+                    T &e = y[i][kk];
+                    e = Elem<Tin>::round(e);  // the value Y holds
+                    if (ok[i] && a < k)
+                        Elem<Tin>::store(Y + (rc[i] - q * rows_n) + rows_n * (q + NN * a), e);
+                }
+        });
+}
+
 // ----------------------------------------------------------------------------
 // Column-group workgroup kernel, 128 < m <= 1024 / G.
 //
@@ -561,9 +626,14 @@ int tsqr_launch_after_first(int dtype, int64_t rows, int64_t m, double *R, int64
 
 bool tsmm_qr_applies(int dtype, int64_t rows, int64_t m, int64_t k, int64_t n_next) {
     const int64_t mn = n_next * k;
-    return (dtype == TTSVD_F64 || dtype == TTSVD_F32 || dtype == TTSVD_BF16) && m >= 1 &&
-           m <= 8 && k >= 1 && (n_next == 2 || n_next == 4) && mn <= 8 && rows % n_next == 0 &&
-           rows / n_next > mn && shape_for(mn).kind == Kind::Rows;
+    if (!((dtype == TTSVD_F64 || dtype == TTSVD_F32 || dtype == TTSVD_BF16) && m >= 1 && k >= 1 &&
+          (n_next == 2 || n_next == 4) && rows % n_next == 0 && rows / n_next > mn))
+        return false;
+    const Shape sh = shape_for(mn);
+    if (mn <= 8) return m <= 8 && sh.kind == Kind::Rows;
+    // the cooperative shapes instantiated below (default configurations)
+    return mn <= 32 && m <= kTqMaxMp && sh.kind == Kind::Coop && sh.nw == 4 &&
+           sh.rpt == (sh.M == 16 ? 16 : 8);
 }
 
 template <typename Tin>
@@ -572,12 +642,40 @@ static int tsmm_qr_typed(const Tin *W, int64_t rows, int64_t m, int64_t ld, cons
                          const Level &l, double *out, int64_t ld_out, int kvalid, hipStream_t s) {
     const int64_t rows_n = rows / n_next;
     const int M = cpow2((int)(n_next * k));
-    dim3 grid((unsigned)ceil_div(l.nslices, kRowsWaves)), block(kRowsWaves * kWave);
     char name[96];
+    const double bytes = (double)rows * (double)(m + k) * sizeof(Tin);
+    const double flops = 2.0 * (double)rows * (double)m * (double)k +
+                         2.0 * (double)rows_n * (double)(n_next * k) * (double)(n_next * k);
+    if (M > 8) {
+        const Shape sh = shape_for(n_next * k);
+        snprintf(name, sizeof(name), "tsmm_qr_coop_kernel<%d, %d, %d, %d, %s>", sh.M, sh.nw, sh.rpt,
+                 (int)n_next, tname<Tin>());
+        prof_begin(s, name, bytes, flops);
+        dim3 grid((unsigned)l.nslices), block(sh.nw * kWave);
+#define TTSVD_TQC(MM, RR, NN)                                                                  \
+    hipLaunchKernelGGL((tsmm_qr_coop_kernel<MM, 4, RR, NN, Tin>), grid, block, 0, s, W, (int)m,  \
+                       ld, V, svc, sva, (int)k, Y, rows_n, l.rows_per_slice, out, ld_out,         \
+                       n_next * k, kvalid)
+        if (M == 16 && n_next == 2)
+            TTSVD_TQC(16, 16, 2);
+        else if (M == 16 && n_next == 4)
+            TTSVD_TQC(16, 16, 4);
+        else if (M == 32 && n_next == 2)
+            TTSVD_TQC(32, 8, 2);
+        else if (M == 32 && n_next == 4)
+            TTSVD_TQC(32, 8, 4);
+        else {
+            prof_end(s);
+            return set_error(TTSVD_EUNSUPPORTED, "tsmm_qr: M = %d, n_next = %lld", M, (long long)n_next);
+        }
+#undef TTSVD_TQC
+        prof_end(s);
+        TTSVD_HIP_TRY(hipGetLastError());
+        return TTSVD_OK;
+    }
+    dim3 grid((unsigned)ceil_div(l.nslices, kRowsWaves)), block(kRowsWaves * kWave);
     snprintf(name, sizeof(name), "tsmm_qr_kernel<%d, %d, 8, %s>", M, (int)n_next, tname<Tin>());
-    prof_begin(s, name, (double)rows * (double)(m + k) * sizeof(Tin),
-               2.0 * (double)rows * (double)m * (double)k +
-                   2.0 * (double)rows_n * (double)(n_next * k) * (double)(n_next * k));
+    prof_begin(s, name, bytes, flops);
 #define TTSVD_TQ(MM, NN)                                                                         \
     hipLaunchKernelGGL((tsmm_qr_kernel<MM, NN, 8, Tin>), grid, block, 0, s, W, (int)m, ld, V, svc, \
                        sva, (int)k, Y, rows_n, l.rows_per_slice, l.nslices, out, ld_out,          \

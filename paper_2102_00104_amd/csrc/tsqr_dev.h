@@ -163,12 +163,13 @@ constexpr size_t tsqr_coop_smem() {
     return sizeof(T) * (2 * RPT * kWave + 2 + NW * kWave);
 }
 
-template <int M, int NW, int RPT, typename Tin>
-__device__ __forceinline__ void tsqr_coop_body(
-    const Tin *__restrict__ W, int64_t rows, int m, int64_t ld, int64_t rows_per_slice,
-    int64_t slice, double *__restrict__ out, int64_t ld_out, int64_t out_row0_stride,
-    int kvalid, void *smem) {
-    using T = typename Elem<Tin>::acc;
+// The body proper, with this wave's columns of the row tile supplied by
+// `load(base, r0, r1, a)`: a[i][kk] = element (base + lane + 64 i, NW kk + w)
+// of the slice [r0, r1), zero for rows >= r1 and columns >= m.
+template <int M, int NW, int RPT, typename T, typename Load>
+__device__ __forceinline__ void tsqr_coop_core(
+    int64_t rows, int m, int64_t rows_per_slice, int64_t slice, double *__restrict__ out,
+    int64_t ld_out, int64_t out_row0_stride, int kvalid, void *smem, Load load) {
     constexpr int MW = M / NW;
     constexpr int RS = (M + kWave - 1) / kWave;  // rows of R per lane
     static_assert(MW * NW == M, "M must be a multiple of NW");
@@ -222,17 +223,7 @@ __device__ __forceinline__ void tsqr_coop_body(
     };
 
     for (int64_t base = r0; base < r1; base += (int64_t)kWave * RPT) {
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const int64_t row = base + lane + (int64_t)kWave * i;
-            const bool ok = row < r1;
-            const int64_t rc = ok ? row : r0;
-#pragma unroll
-            for (int kk = 0; kk < MW; ++kk) {
-                const int c = NW * kk + w;
-                a[i][kk] = load_or_zero(W + rc + ld * (c < m ? c : 0), ok && c < m);
-            }
-        }
+        load(base, r0, r1, a);
         if (w == 0) reflector(std::integral_constant<int, 0>{}, 0);
         static_for<0, MW>([&](auto jjc) {
             constexpr int jj = decltype(jjc)::value;
@@ -305,6 +296,32 @@ __device__ __forceinline__ void tsqr_coop_body(
             }
         }
     }
+}
+
+template <int M, int NW, int RPT, typename Tin>
+__device__ __forceinline__ void tsqr_coop_body(
+    const Tin *__restrict__ W, int64_t rows, int m, int64_t ld, int64_t rows_per_slice,
+    int64_t slice, double *__restrict__ out, int64_t ld_out, int64_t out_row0_stride,
+    int kvalid, void *smem) {
+    using T = typename Elem<Tin>::acc;
+    constexpr int MW = M / NW;
+    tsqr_coop_core<M, NW, RPT, T>(
+        rows, m, rows_per_slice, slice, out, ld_out, out_row0_stride, kvalid, smem,
+        [&](int64_t base, int64_t r0, int64_t r1, T (&a)[RPT][MW]) {
+            const int lane = lane_id();
+            const int w = thread_id() / kWave;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int64_t row = base + lane + (int64_t)kWave * i;
+                const bool ok = row < r1;
+                const int64_t rc = ok ? row : r0;
+#pragma unroll
+                for (int kk = 0; kk < MW; ++kk) {
+                    const int c = NW * kk + w;
+                    a[i][kk] = load_or_zero(W + rc + ld * (c < m ? c : 0), ok && c < m);
+                }
+            }
+        });
 }
 
 // ----------------------------------------------------------------------------

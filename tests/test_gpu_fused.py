@@ -1,16 +1,18 @@
 """GPU test of the product fused with the next step's first TSQR level.
 
-For W with m <= 8 columns and n_next in {2, 4}, n_next r <= 8, the
-decomposition builds each row tile of the next unfolding Y = reshape(W V)
-(Sec. 4.1.2) in registers, stores it and runs the flat Householder reduction
-of Sec. 3.2 on the same registers.  The product accumulates in the order of
-the TSMM kernel and the reduction is the rows body itself, so the result must
+For n_next in {2, 4} and a next unfolding of n_next r <= 32 columns (W with
+m <= 8 columns up to 8, m <= 32 beyond), the decomposition builds each row
+tile of the next unfolding Y = reshape(W V) (Sec. 4.1.2) in registers,
+stores it and runs the flat Householder reduction of Sec. 3.2 on the same
+registers.  The product accumulates in the order of the TSMM kernel and the
+reduction is the rows or cooperative body itself, so the result must
 equal, bit for bit, the decomposition with separate launches, which a child
 process computes with TTSVD_TSMM_QR=0 on the same input (the switch is read
-once per process).  Shapes: n = 2 (steps 1 and 2 of a QTT fuse: 2 x 2 -> 4
-and 4 x 4 -> 8 columns) and n = 4 with r_max = 2 (4 x 2 -> 8), in FP64,
-FP32 and BF16 storage; the input spans many row tiles and slices and ends
-in a ragged tile.
+once per process).  Shapes: n = 2 (the first steps of a QTT: 2 x 2 -> 4,
+4 x 4 -> 8, 8 x 8 -> 16, 16 x 16 -> 32 columns) and n = 4 (4 x 2 -> 8,
+4 x 4 -> 16, 16 x 8 -> 32), in FP64, FP32 and BF16 storage, with r < KB
+(3 of 4 columns per block) once; the inputs span many row tiles and slices
+and end in ragged tiles.
 """
 import os
 import subprocess
@@ -31,7 +33,8 @@ import paper_2102_00104_amd as tt  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CASES = [([2] * 21, 8, "f64"), ([2] * 20 + [3], 6, "f32"), ([2] * 21, 8, "bf16"),
-         ([4] * 10, 2, "f64")]
+         ([4] * 10, 2, "f64"), ([2] * 22, 16, "f64"), ([2] * 21, 16, "f32"),
+         ([4] * 9, 4, "f64"), ([4] * 9, 8, "bf16")]
 TORCH_DT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
 
 CHILD = r"""
@@ -68,7 +71,7 @@ def test_fused_equals_separate_launches(dims, r_max, name, tmp_path):
     finally:
         tt.ttsvd_profile_enable(False)
         tt.ttsvd_profile_reset()
-    assert any(n.startswith("tsmm_qr_kernel") for n in names), names
+    assert any(n.startswith("tsmm_qr") for n in names), names
     out = str(tmp_path / "separate.npz")
     env = dict(os.environ, TTSVD_TSMM_QR="0")
     print("child: separate launches for", dims, r_max, name, flush=True)
