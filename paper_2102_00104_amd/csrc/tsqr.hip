@@ -13,6 +13,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -43,6 +44,18 @@ __global__ __launch_bounds__(NW *kWave) void tsqr_coop_kernel(
     (void)nslices;
     tsqr_coop_body<M, NW, RPT, Tin>(W, rows, m, ld, rows_per_slice, blockIdx.x, out, ld_out,
                                     out_row0_stride, kvalid, smem);
+}
+
+// Tree levels of m = 64: the tile is 8 stacked triangular factors, and the
+// reflectors skip the rows that are still zero (tsqr_coop_core with TRI).
+__global__ __launch_bounds__(8 * kWave) void tsqr_coop_tri_kernel(
+    const double *__restrict__ W, int64_t rows, int m, int64_t ld, int64_t rows_per_slice,
+    int64_t nslices, double *__restrict__ out, int64_t ld_out, int64_t out_row0_stride,
+    int kvalid) {
+    __shared__ __attribute__((aligned(16))) char smem[tsqr_coop_smem<64, 8, 8, double>()];
+    (void)nslices;
+    tsqr_coop_body<64, 8, 8, double, true>(W, rows, m, ld, rows_per_slice, blockIdx.x, out,
+                                           ld_out, out_row0_stride, kvalid, smem);
 }
 
 // Product and first TSQR level of the next unfolding in one pass (the TSMM of
@@ -467,6 +480,9 @@ int launch_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level 
     const Shape sh = shape_for(m);
     if (sh.kind == Kind::Rows)
         snprintf(name, sizeof(name), "tsqr_rows_kernel<%d, %d, %s>", sh.M, sh.rpt, tname<Tin>());
+    else if (sh.kind == Kind::Coop && tree && m == 64 && sh.nw == 8 && sh.rpt == 8 &&
+             std::is_same<Tin, double>::value && l.rows_per_slice % 64 == 0)
+        snprintf(name, sizeof(name), "tsqr_coop_tri_kernel");
     else if (sh.kind == Kind::Coop)
         snprintf(name, sizeof(name), "tsqr_coop_kernel<%d, %d, %d, %s>", sh.M, sh.nw, sh.rpt,
                  tname<Tin>());
@@ -502,6 +518,11 @@ int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Le
                 return set_error(TTSVD_EUNSUPPORTED, "tsqr: bad column bucket %d", sh.M);
         }
 #undef TTSVD_ROWS_CASE
+    } else if (sh.kind == Kind::Coop && tree && m == 64 && sh.nw == 8 && sh.rpt == 8 &&
+               std::is_same<Tin, double>::value && l.rows_per_slice % 64 == 0) {
+        hipLaunchKernelGGL(tsqr_coop_tri_kernel, dim3((unsigned)l.nslices), dim3(8 * kWave), 0, s,
+                           (const double *)W, rows, (int)m, ld, l.rows_per_slice, l.nslices, out,
+                           ld_out, out_stride, kvalid);
     } else if (sh.kind == Kind::Coop) {
         dim3 grid((unsigned)l.nslices), block(sh.nw * kWave);
 #define TTSVD_COOP_LAUNCH(MM, NN, RR)                                                         \

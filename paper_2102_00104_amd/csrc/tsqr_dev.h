@@ -166,7 +166,15 @@ constexpr size_t tsqr_coop_smem() {
 // The body proper, with this wave's columns of the row tile supplied by
 // `load(base, r0, r1, a)`: a[i][kk] = element (base + lane + 64 i, NW kk + w)
 // of the slice [r0, r1), zero for rows >= r1 and columns >= m.
-template <int M, int NW, int RPT, typename T, typename Load>
+//
+// TRI (M = 64, NW = RPT = 8): the tile is a stack of 8 upper-triangular
+// 64 x 64 factors (a tree level), loaded so that register i of a lane holds
+// rows 8 i .. 8 i + 7 of its factor (a[i][kk] = row 64 (lane / 8) + 8 i +
+// lane mod 8 of the tile).  Column j of every factor is zero below row j and
+// stays so (a reflector for column j only mixes rows <= j of each factor), so
+// reflector j and its dot products and updates involve registers i <= j / 8
+// only: the others are skipped.
+template <int M, int NW, int RPT, typename T, typename Load, bool TRI = false>
 __device__ __forceinline__ void tsqr_coop_core(
     int64_t rows, int m, int64_t rows_per_slice, int64_t slice, double *__restrict__ out,
     int64_t ld_out, int64_t out_row0_stride, int kvalid, void *smem, Load load) {
@@ -174,6 +182,9 @@ __device__ __forceinline__ void tsqr_coop_core(
     constexpr int RS = (M + kWave - 1) / kWave;  // rows of R per lane
     static_assert(MW * NW == M, "M must be a multiple of NW");
     static_assert(RS == 1 || kWave % NW == 0, "row sets need NW | 64");
+    static_assert(!TRI || (M == 64 && NW == 8 && RPT == 8), "stacked-factor layout");
+    // registers of a lane that can be nonzero in the columns of slot S
+    auto nact = [](auto slot_c) constexpr { return TRI ? decltype(slot_c)::value + 1 : RPT; };
     T(*vbuf)[RPT][kWave] = reinterpret_cast<T(*)[RPT][kWave]>(smem);
     T *vrbuf = reinterpret_cast<T *>(smem) + 2 * RPT * kWave;
 
@@ -199,10 +210,11 @@ __device__ __forceinline__ void tsqr_coop_core(
     auto reflector = [&](auto slot_c, int jn) {
         constexpr int S = decltype(slot_c)::value;
         constexpr int RSET = (NW * S) / kWave;
+        constexpr int NA = nact(slot_c);
         const bool own = (lane == (jn & (kWave - 1)));
         T s = T(0);
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) s = fma(a[i][S], a[i][S], s);
+        for (int i = 0; i < NA; ++i) s = fma(a[i][S], a[i][S], s);
         const T rjj = own ? R[RSET][S] : T(0);
         s = fma(rjj, rjj, s);
         s = wave_sum(s);
@@ -215,7 +227,7 @@ __device__ __forceinline__ void tsqr_coop_core(
         const T beta = rsqrt_nr(t);
         const int buf = jn & 1;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) vbuf[buf][i][lane] = beta * a[i][S];
+        for (int i = 0; i < NA; ++i) vbuf[buf][i][lane] = beta * a[i][S];
         if (own) {
             vrbuf[buf] = beta * (u1 - alpha);
             R[RSET][S] = alpha;
@@ -229,14 +241,15 @@ __device__ __forceinline__ void tsqr_coop_core(
             constexpr int jj = decltype(jjc)::value;
             constexpr int NT = MW - jj;  // slots jj..MW-1 may trail column j
             constexpr int RSET = (NW * jj) / kWave;  // row set of row j
+            constexpr int NA = nact(jjc);  // registers where reflector j can be nonzero
             for (int o = 0; o < NW; ++o) {
                 const int j = NW * jj + o;
                 if (j >= m) break;
                 const int buf = j & 1;
                 __syncthreads();  // reflector j is in vbuf[buf]
-                T v[RPT];
+                T v[NA];
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) v[i] = vbuf[buf][i][lane];
+                for (int i = 0; i < NA; ++i) v[i] = vbuf[buf][i][lane];
                 const T vr = (lane == (j & (kWave - 1))) ? vrbuf[buf] : T(0);
                 const bool first = (w > o);  // slot jj trails column j only in later waves
                 T p[NT];
@@ -244,7 +257,7 @@ __device__ __forceinline__ void tsqr_coop_core(
                 for (int q = 0; q < NT; ++q) {
                     T acc = vr * R[RSET][jj + q];
 #pragma unroll
-                    for (int i = 0; i < RPT; ++i) acc = fma(v[i], a[i][jj + q], acc);
+                    for (int i = 0; i < NA; ++i) acc = fma(v[i], a[i][jj + q], acc);
                     p[q] = (q == 0 && !first) ? T(0) : acc;
                 }
                 wave_allreduce_vec<NT>(p, lds);
@@ -253,7 +266,7 @@ __device__ __forceinline__ void tsqr_coop_core(
                     for (int qq = 0; qq < NT; ++qq) {
                         if (qq == q) {
 #pragma unroll
-                            for (int i = 0; i < RPT; ++i) a[i][jj + qq] = fma(-p[qq], v[i], a[i][jj + qq]);
+                            for (int i = 0; i < NA; ++i) a[i][jj + qq] = fma(-p[qq], v[i], a[i][jj + qq]);
                             R[RSET][jj + qq] = fma(-p[qq], vr, R[RSET][jj + qq]);
                         }
                     }
@@ -298,21 +311,20 @@ __device__ __forceinline__ void tsqr_coop_core(
     }
 }
 
-template <int M, int NW, int RPT, typename Tin>
+template <int M, int NW, int RPT, typename Tin, bool TRI = false>
 __device__ __forceinline__ void tsqr_coop_body(
     const Tin *__restrict__ W, int64_t rows, int m, int64_t ld, int64_t rows_per_slice,
     int64_t slice, double *__restrict__ out, int64_t ld_out, int64_t out_row0_stride,
     int kvalid, void *smem) {
     using T = typename Elem<Tin>::acc;
     constexpr int MW = M / NW;
-    tsqr_coop_core<M, NW, RPT, T>(
-        rows, m, rows_per_slice, slice, out, ld_out, out_row0_stride, kvalid, smem,
-        [&](int64_t base, int64_t r0, int64_t r1, T (&a)[RPT][MW]) {
+    auto load = [&](int64_t base, int64_t r0, int64_t r1, T (&a)[RPT][MW]) {
             const int lane = lane_id();
             const int w = thread_id() / kWave;
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                const int64_t row = base + lane + (int64_t)kWave * i;
+                const int64_t row = TRI ? base + 64 * (lane >> 3) + 8 * i + (lane & 7)
+                                        : base + lane + (int64_t)kWave * i;
                 const bool ok = row < r1;
                 const int64_t rc = ok ? row : r0;
 #pragma unroll
@@ -321,7 +333,9 @@ __device__ __forceinline__ void tsqr_coop_body(
                     a[i][kk] = load_or_zero(W + rc + ld * (c < m ? c : 0), ok && c < m);
                 }
             }
-        });
+        };
+    tsqr_coop_core<M, NW, RPT, T, decltype(load), TRI>(
+        rows, m, rows_per_slice, slice, out, ld_out, out_row0_stride, kvalid, smem, load);
 }
 
 // ----------------------------------------------------------------------------
