@@ -377,6 +377,16 @@ CoopCfg coop_cfg(int M) {
     return M == 16 ? kCoop16[v] : M == 32 ? kCoop32[v] : M == 64 ? kCoop64[v] : kCoop128[v];
 }
 
+// TTSVD_TSQR_TRI=0 runs the tree levels of m = 64 with the general
+// cooperative kernel instead of the stacked-triangle one (a tuning override).
+bool tri_enabled() {
+    static bool v = [] {
+        const char *e = getenv("TTSVD_TSQR_TRI");
+        return !(e && atoi(e) == 0);
+    }();
+    return v;
+}
+
 // TTSVD_TSQR_BLK=0 selects the column-group kernel for 128 < m <= 512 instead
 // of the blocked one (a tuning override).
 bool blk_enabled() {
@@ -480,7 +490,7 @@ int launch_level(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Level 
     const Shape sh = shape_for(m);
     if (sh.kind == Kind::Rows)
         snprintf(name, sizeof(name), "tsqr_rows_kernel<%d, %d, %s>", sh.M, sh.rpt, tname<Tin>());
-    else if (sh.kind == Kind::Coop && tree && m == 64 && sh.nw == 8 && sh.rpt == 8 &&
+    else if (sh.kind == Kind::Coop && tree && m == 64 && sh.nw == 8 && sh.rpt == 8 && tri_enabled() &&
              std::is_same<Tin, double>::value && l.rows_per_slice % 64 == 0)
         snprintf(name, sizeof(name), "tsqr_coop_tri_kernel");
     else if (sh.kind == Kind::Coop)
@@ -518,7 +528,7 @@ int launch_level_raw(const Tin *W, int64_t rows, int64_t m, int64_t ld, const Le
                 return set_error(TTSVD_EUNSUPPORTED, "tsqr: bad column bucket %d", sh.M);
         }
 #undef TTSVD_ROWS_CASE
-    } else if (sh.kind == Kind::Coop && tree && m == 64 && sh.nw == 8 && sh.rpt == 8 &&
+    } else if (sh.kind == Kind::Coop && tree && m == 64 && sh.nw == 8 && sh.rpt == 8 && tri_enabled() &&
                std::is_same<Tin, double>::value && l.rows_per_slice % 64 == 0) {
         hipLaunchKernelGGL(tsqr_coop_tri_kernel, dim3((unsigned)l.nslices), dim3(8 * kWave), 0, s,
                            (const double *)W, rows, (int)m, ld, l.rows_per_slice, l.nslices, out,
